@@ -1,0 +1,299 @@
+/*
+ * fbs_oracle.c - plain FP64 CPU oracle for fast bilateral stereo (FBS).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library.  The GPU library never
+ * links it; the two share no source, header, table or helper.
+ *
+ * Everything is evaluated in double precision, directly from the definitions
+ * of "Real-Time Subpixel Fast Bilateral Stereo" (Fan et al.), with the left
+ * image as the reference view:
+ *
+ *   cost       Section II-A.  Either the truncated absolute difference (TAD)
+ *              min(mean_ch |L(x,y) - R(x-d,y)|, tau), or the normalised
+ *              cross-correlation of Eqs. (1)-(3) turned into a cost 1 - c.
+ *   weights    Section II-B, Eqs. (7) and (8): w = omega_d * omega_r with
+ *              omega_d = exp(-(dx^2+dy^2)/gamma_d^2) and
+ *              omega_r = exp(-(i(q)-i(p))^2/gamma_r^2).
+ *   aggregate  Section II-B, Eq. (6): A(p,d) = sum_t w c / sum_t w.
+ *   WTA        Section II-C: the disparity of the lowest aggregated cost.
+ *   subpixel   Section II-D, Eq. (10): parabola through d*-1, d*, d*+1.
+ *
+ * Readings where the paper is silent (each one is listed in the design notes):
+ *   - right column x-d outside the image: TAD cost = tau, NCC cost = 2;
+ *   - NCC block pixels outside the image: clamp-to-edge coordinates;
+ *   - NCC block with zero variance: c = 0 (cost 1);
+ *   - RGB: TAD averages |diff| over channels before the cap; the range weight
+ *     uses the mean over channels of the squared differences;
+ *   - window taps outside the image are left out of both sums of Eq. (6);
+ *   - gamma values are used as printed (no factor 2); gamma = +inf gives 1;
+ *   - WTA ties go to the lowest d; Eq. (10) is applied to the aggregated
+ *     costs, and returns d* at d_min, d_max or when its denominator is <= 0.
+ *
+ * Volumes are [D][H][W] with index d - d_min; weights are [H][W][(2r+1)^2]
+ * in row-major tap order (dy outer, dx inner).  Images are HWC uint8 with a
+ * row stride in bytes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t width, height, channels, row_stride;
+    int32_t d_min, d_max, radius, ncc_radius;
+    int32_t cost_type; /* 0 = TAD, 1 = NCC */
+    int32_t reserved;
+    double gamma_d, gamma_r, tau;
+} orc_params;
+
+enum { ORC_TAD = 0, ORC_NCC = 1 };
+
+static int orc_check(const orc_params* p)
+{
+    if (!p) return -1;
+    if (p->width <= 0 || p->height <= 0) return -1;
+    if (p->channels != 1 && p->channels != 3) return -1;
+    if (p->row_stride < p->width * p->channels) return -1;
+    if (p->d_min < 0 || p->d_max < p->d_min || p->d_max >= p->width) return -1;
+    if (p->radius < 0) return -1;
+    if (!(p->gamma_d > 0.0) || !(p->gamma_r > 0.0)) return -1;
+    if (p->cost_type == ORC_TAD) {
+        if (!(p->tau > 0.0)) return -1;
+    } else if (p->cost_type == ORC_NCC) {
+        if (p->channels != 1 || p->ncc_radius < 0) return -1;
+    } else {
+        return -1;
+    }
+    return 0;
+}
+
+static inline double pix(const uint8_t* img, const orc_params* p, int x, int y, int ch)
+{
+    return (double)img[(size_t)y * (size_t)p->row_stride + (size_t)x * (size_t)p->channels + ch];
+}
+
+static inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Truncated absolute difference between L(x,y) and R(x-d,y). */
+static double cost_tad(const orc_params* p, const uint8_t* L, const uint8_t* R,
+                       int x, int y, int d)
+{
+    if (x - d < 0 || x - d >= p->width) return p->tau;
+    double s = 0.0;
+    for (int ch = 0; ch < p->channels; ++ch)
+        s += fabs(pix(L, p, x, y, ch) - pix(R, p, x - d, y, ch));
+    double m = s / (double)p->channels;
+    return m < p->tau ? m : p->tau;
+}
+
+/* Eqs. (1)-(3): correlation of the (2*varrho+1)^2 blocks centred on (u,v) in
+ * the left image and (u-d,v) in the right image, returned as the cost 1 - c. */
+static double cost_ncc(const orc_params* p, const uint8_t* L, const uint8_t* R,
+                       int u, int v, int d)
+{
+    if (u - d < 0 || u - d >= p->width) return 2.0;
+    const int rr = p->ncc_radius;
+    const double n = (double)((2 * rr + 1) * (2 * rr + 1));
+    double sl = 0, sr = 0, sll = 0, srr = 0, slr = 0;
+    for (int y = v - rr; y <= v + rr; ++y) {
+        for (int x = u - rr; x <= u + rr; ++x) {
+            int yc = clampi(y, 0, p->height - 1);
+            int xl = clampi(x, 0, p->width - 1);
+            int xr = clampi(x - d, 0, p->width - 1);
+            double il = pix(L, p, xl, yc, 0);
+            double ir = pix(R, p, xr, yc, 0);
+            sl += il; sr += ir; sll += il * il; srr += ir * ir; slr += il * ir;
+        }
+    }
+    double mu_l = sl / n, mu_r = sr / n;
+    double var_l = sll / n - mu_l * mu_l;   /* sigma_l^2, Eq. (2) */
+    double var_r = srr / n - mu_r * mu_r;   /* sigma_r^2, Eq. (3) */
+    double c = 0.0;
+    if (var_l > 0.0 && var_r > 0.0)
+        c = (slr - n * mu_l * mu_r) / (n * sqrt(var_l) * sqrt(var_r));
+    return 1.0 - c;
+}
+
+static double cost_at(const orc_params* p, const uint8_t* L, const uint8_t* R,
+                      int x, int y, int d)
+{
+    return p->cost_type == ORC_NCC ? cost_ncc(p, L, R, x, y, d) : cost_tad(p, L, R, x, y, d);
+}
+
+/* Eqs. (7)-(8): weight of tap q = p + (dx,dy) for centre p; 0 off-image. */
+static double weight_at(const orc_params* p, const uint8_t* L, int u, int v, int dx, int dy)
+{
+    int x = u + dx, y = v + dy;
+    if (x < 0 || x >= p->width || y < 0 || y >= p->height) return 0.0;
+    double dist2 = (double)(dx * dx + dy * dy);
+    double wd = exp(-dist2 / (p->gamma_d * p->gamma_d));
+    double diff2 = 0.0;
+    for (int ch = 0; ch < p->channels; ++ch) {
+        double t = pix(L, p, x, y, ch) - pix(L, p, u, v, ch);
+        diff2 += t * t;
+    }
+    diff2 /= (double)p->channels;
+    double wr = exp(-diff2 / (p->gamma_r * p->gamma_r));
+    return wd * wr;
+}
+
+int orc_cost(const orc_params* p, const uint8_t* L, const uint8_t* R, double* cost)
+{
+    if (orc_check(p)) return -1;
+    const int W = p->width, H = p->height, D = p->d_max - p->d_min + 1;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y)
+        for (int k = 0; k < D; ++k)
+            for (int x = 0; x < W; ++x)
+                cost[((size_t)k * H + y) * W + x] = cost_at(p, L, R, x, y, p->d_min + k);
+    return 0;
+}
+
+int orc_weights(const orc_params* p, const uint8_t* L, double* w)
+{
+    if (orc_check(p)) return -1;
+    const int W = p->width, H = p->height, r = p->radius, T = (2 * r + 1) * (2 * r + 1);
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            double* wp = w + ((size_t)y * W + x) * T;
+            int t = 0;
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx)
+                    wp[t++] = weight_at(p, L, x, y, dx, dy);
+        }
+    return 0;
+}
+
+/* Eq. (6) over a materialised cost volume and weight field. */
+int orc_aggregate(const orc_params* p, const double* cost, const double* w, double* agg)
+{
+    if (orc_check(p)) return -1;
+    const int W = p->width, H = p->height, r = p->radius, T = (2 * r + 1) * (2 * r + 1);
+    const int D = p->d_max - p->d_min + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const double* wp = w + ((size_t)y * W + x) * T;
+            double den = 0.0;
+            for (int t = 0; t < T; ++t) den += wp[t];
+            for (int k = 0; k < D; ++k) {
+                const double* plane = cost + (size_t)k * H * W;
+                double num = 0.0;
+                int t = 0;
+                for (int dy = -r; dy <= r; ++dy)
+                    for (int dx = -r; dx <= r; ++dx, ++t) {
+                        int qx = x + dx, qy = y + dy;
+                        if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                        num += wp[t] * plane[(size_t)qy * W + qx];
+                    }
+                agg[((size_t)k * H + y) * W + x] = num / den;
+            }
+        }
+    return 0;
+}
+
+/* WTA (Section II-C) and the parabola of Eq. (10) for one pixel; a[k] is the
+ * aggregated cost at d = d_min + k, the stride between consecutive d is sd. */
+static void wta_subpixel_one(const orc_params* p, const double* a, size_t sd,
+                             int32_t* disp, double* disp_sub)
+{
+    const int D = p->d_max - p->d_min + 1;
+    int best = 0;
+    for (int k = 1; k < D; ++k)
+        if (a[(size_t)k * sd] < a[(size_t)best * sd]) best = k;
+    double ds = (double)(p->d_min + best);
+    if (best > 0 && best < D - 1) {
+        double cm = a[(size_t)(best - 1) * sd];
+        double c0 = a[(size_t)best * sd];
+        double cp = a[(size_t)(best + 1) * sd];
+        double den = 2.0 * cm + 2.0 * cp - 4.0 * c0;
+        if (den > 0.0) ds += (cm - cp) / den;
+    }
+    *disp = p->d_min + best;
+    *disp_sub = ds;
+}
+
+int orc_wta_subpixel(const orc_params* p, const double* agg, int32_t* disp, double* disp_sub)
+{
+    if (orc_check(p)) return -1;
+    const int W = p->width, H = p->height;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            size_t i = (size_t)y * W + x;
+            wta_subpixel_one(p, agg + i, (size_t)W * H, disp + i, disp_sub + i);
+        }
+    return 0;
+}
+
+/* The whole left-reference pipeline: cost, weights, Eq. (6), WTA, Eq. (10).
+ * agg_out may be NULL. Returns -2 when the volumes cannot be allocated. */
+int orc_fbs(const orc_params* p, const uint8_t* L, const uint8_t* R,
+            int32_t* disp, double* disp_sub, double* agg_out)
+{
+    if (orc_check(p)) return -1;
+    const size_t N = (size_t)p->width * p->height;
+    const size_t D = (size_t)(p->d_max - p->d_min + 1);
+    const size_t T = (size_t)(2 * p->radius + 1) * (2 * p->radius + 1);
+    double* cost = (double*)malloc(N * D * sizeof(double));
+    double* w = (double*)malloc(N * T * sizeof(double));
+    double* agg = agg_out ? agg_out : (double*)malloc(N * D * sizeof(double));
+    int rc = 0;
+    if (!cost || !w || !agg) {
+        rc = -2;
+    } else {
+        orc_cost(p, L, R, cost);
+        orc_weights(p, L, w);
+        orc_aggregate(p, cost, w, agg);
+        orc_wta_subpixel(p, agg, disp, disp_sub);
+    }
+    free(cost);
+    free(w);
+    if (!agg_out) free(agg);
+    return rc;
+}
+
+/* The same pipeline evaluated at n chosen pixels only (xs[i], ys[i]), for
+ * images too large for full volumes.  agg is [n][D]. */
+int orc_fbs_pixels(const orc_params* p, const uint8_t* L, const uint8_t* R, int32_t n,
+                   const int32_t* xs, const int32_t* ys, double* agg, int32_t* disp,
+                   double* disp_sub)
+{
+    if (orc_check(p)) return -1;
+    const int r = p->radius, D = p->d_max - p->d_min + 1;
+    for (int i = 0; i < n; ++i)
+        if (xs[i] < 0 || xs[i] >= p->width || ys[i] < 0 || ys[i] >= p->height) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < n; ++i) {
+        const int x = xs[i], y = ys[i];
+        double* a = agg + (size_t)i * D;
+        double den = 0.0;
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) den += weight_at(p, L, x, y, dx, dy);
+        for (int k = 0; k < D; ++k) {
+            double num = 0.0;
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx) {
+                    int qx = x + dx, qy = y + dy;
+                    if (qx < 0 || qx >= p->width || qy < 0 || qy >= p->height) continue;
+                    num += weight_at(p, L, x, y, dx, dy) * cost_at(p, L, R, qx, qy, p->d_min + k);
+                }
+            a[k] = num / den;
+        }
+        wta_subpixel_one(p, a, 1, disp + i, disp_sub + i);
+    }
+    return 0;
+}
+
+/* Number of OpenMP threads the oracle runs on. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

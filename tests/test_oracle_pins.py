@@ -1,0 +1,456 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's code: each check reaches the expected
+value by another route (a hand-worked example, a closed form, a library
+routine such as numpy's Pearson correlation or scipy's convolution, an
+integral-image box filter, or an exact-recovery scene), chosen so that a
+plausible slip in the oracle - a dropped term, a wrong sign or index, a
+transposed operand, a factor 2 in a Gaussian - fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+from oracle import NCC, TAD, Problem
+from paper_1807_02044_amd import scenes
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+# ---------------------------------------------------------------- a1: TAD cost
+
+
+def test_tad_hand_worked_gray():
+    """Section II-A cost step with the truncated absolute difference, by hand."""
+    L = np.array([[10, 50, 200, 0]], dtype=np.uint8)
+    R = np.array([[12, 90, 30, 255]], dtype=np.uint8)
+    pb = Problem(0, 2, 0, 1.0, 1.0, tau=40.0)
+    c = oracle.cost(pb, L, R)
+    # C(x, d) = min(|L(x) - R(x - d)|, 40); 40 where x - d < 0
+    want = np.array([
+        [2, 40, 40, 40],        # d=0: |10-12|, |50-90|, |200-30|, |0-255|
+        [40, 38, 40, 30],       # d=1: off, |50-12|, |200-90|, |0-30|
+        [40, 40, 40, 40],       # d=2: off, off, |200-12|, |0-90|
+    ], dtype=np.float64)
+    np.testing.assert_array_equal(c[:, 0, :], want)
+
+
+def test_tad_hand_worked_rgb_mean_then_cap():
+    """RGB cost is the channel mean of |diff|, then the cap."""
+    L = np.array([[[10, 20, 30], [0, 0, 0]]], dtype=np.uint8)
+    R = np.array([[[13, 14, 30], [100, 0, 50]]], dtype=np.uint8)
+    pb = Problem(0, 1, 0, 1.0, 1.0, tau=40.0)
+    c = oracle.cost(pb, L, R)
+    assert c[0, 0, 0] == pytest.approx((3 + 6 + 0) / 3.0, abs=0)   # 3
+    assert c[0, 0, 1] == 40.0                                       # mean 50 -> cap 40
+    assert c[1, 0, 0] == 40.0                                       # off-image
+    assert c[1, 0, 1] == pytest.approx((13 + 14 + 30) / 3.0, abs=1e-15)   # L(1) vs R(0): 19
+
+
+def test_tad_matches_shifted_slices():
+    """Vectorised shifted-slice TAD (a different indexing route) equals the oracle."""
+    rng = _rng(5)
+    L = rng.integers(0, 256, (9, 23), dtype=np.uint8)
+    R = rng.integers(0, 256, (9, 23), dtype=np.uint8)
+    pb = Problem(2, 9, 0, 1.0, 1.0, tau=33.0)
+    c = oracle.cost(pb, L, R)
+    Lf, Rf = L.astype(np.float64), R.astype(np.float64)
+    for k, d in enumerate(range(pb.d_min, pb.d_max + 1)):
+        want = np.full(L.shape, 33.0)
+        want[:, d:] = np.minimum(np.abs(Lf[:, d:] - Rf[:, :L.shape[1] - d]), 33.0)
+        np.testing.assert_array_equal(c[k], want)
+
+
+# ---------------------------------------------------------------- a2: NCC cost
+
+
+def _blocks(img, u, v, rr):
+    p = np.pad(img.astype(np.float64), rr, mode="edge")
+    return p[v:v + 2 * rr + 1, u:u + 2 * rr + 1].ravel()
+
+
+def test_ncc_is_one_minus_pearson_correlation():
+    """Eq. (1) is the Pearson correlation of the two blocks (numpy corrcoef)."""
+    rng = _rng(11)
+    L = rng.integers(0, 256, (12, 20), dtype=np.uint8)
+    R = rng.integers(0, 256, (12, 20), dtype=np.uint8)
+    pb = Problem(0, 5, 0, 1.0, 1.0, cost_type=NCC, ncc_radius=1)
+    c = oracle.cost(pb, L, R)
+    for k, d in enumerate(range(0, 6)):
+        for v in range(12):
+            for u in range(20):
+                if u - d < 0:
+                    assert c[k, v, u] == 2.0
+                    continue
+                bl = _blocks(L, u, v, 1)
+                # the right block is centred on u - d, clamp-to-edge
+                br = _blocks(R, u - d, v, 1)
+                want = 1.0 - np.corrcoef(bl, br)[0, 1]
+                assert c[k, v, u] == pytest.approx(want, abs=1e-12)
+
+
+def test_ncc_radius2_and_special_cases():
+    rng = _rng(12)
+    L = rng.integers(0, 256, (10, 14), dtype=np.uint8)
+    R = rng.integers(0, 256, (10, 14), dtype=np.uint8)
+    pb = Problem(0, 3, 0, 1.0, 1.0, cost_type=NCC, ncc_radius=2)
+    c = oracle.cost(pb, L, R)
+    u, v, d = 9, 5, 2
+    want = 1.0 - np.corrcoef(_blocks(L, u, v, 2), _blocks(R, u - d, v, 2))[0, 1]
+    assert c[d, v, u] == pytest.approx(want, abs=1e-12)
+    # a flat block has no correlation: cost 1
+    Lf = L.copy()
+    Lf[:, :] = 77
+    cf = oracle.cost(pb, Lf, R)
+    assert np.all(cf[:, :, 3:] == 1.0)
+    # a block matched with itself: c = 1, cost 0
+    ci = oracle.cost(pb, L, L)
+    assert np.all(np.abs(ci[0]) < 1e-12)
+
+
+def test_ncc_gain_bias_invariance():
+    """Correlation ignores an intensity gain and bias of the right view."""
+    rng = _rng(13)
+    L = rng.integers(0, 200, (10, 16), dtype=np.uint8)
+    R = rng.integers(0, 120, (10, 16), dtype=np.uint8)
+    pb = Problem(0, 4, 0, 1.0, 1.0, cost_type=NCC)
+    base = oracle.cost(pb, L, R)
+    biased = oracle.cost(pb, L, (R + 50).astype(np.uint8))
+    gained = oracle.cost(pb, L, (R * 2).astype(np.uint8))
+    np.testing.assert_allclose(biased, base, atol=1e-12)
+    np.testing.assert_allclose(gained, base, atol=1e-12)
+
+
+# ---------------------------------------------------------------- a3: weights
+
+
+def test_weights_hand_worked_two_rows():
+    """Eqs. (7)-(8) at one centre of a 2x3 image, each weight derived by hand."""
+    L = np.array([[100, 110, 100], [110, 100, 130]], dtype=np.uint8)
+    pb = Problem(0, 0, 1, gamma_d=2.0, gamma_r=10.0)
+    w = oracle.weights(pb, L)[0, 1].reshape(3, 3)      # centre (x=1, y=0), L = 110
+    e = math.exp
+    want = np.array([
+        [0.0, 0.0, 0.0],                                 # row y=-1 is off-image
+        [e(-1 / 4) * e(-1), 1.0, e(-1 / 4) * e(-1)],     # |dx|=1: dist 1, |dI| = 10
+        [e(-2 / 4) * 1.0, e(-1 / 4) * e(-1), e(-2 / 4) * e(-4)],   # dI = 0, 10, 20
+    ])
+    np.testing.assert_allclose(w, want, rtol=1e-15, atol=0)
+
+
+def test_weights_rgb_mean_of_squares():
+    L = np.array([[[10, 20, 30], [13, 26, 30]]], dtype=np.uint8)
+    pb = Problem(0, 0, 1, gamma_d=math.inf, gamma_r=3.0)
+    w = oracle.weights(pb, L)[0, 0].reshape(3, 3)
+    # (3^2 + 6^2 + 0^2) / 3 = 15 ; exp(-15/9)
+    assert w[1, 2] == pytest.approx(math.exp(-15.0 / 9.0), rel=1e-15)
+    assert w[1, 1] == 1.0
+
+
+# ------------------------------------------------------- a4: aggregation, Eq. (6)
+
+
+def test_aggregate_hand_worked():
+    """Eq. (6) at every pixel of the 2x3 example with an injected cost plane."""
+    L = np.array([[100, 110, 100], [110, 100, 130]], dtype=np.uint8)
+    pb = Problem(0, 0, 1, gamma_d=2.0, gamma_r=10.0)
+    C = np.array([[[1.0, 2.0, 3.0], [4.0, 5.0, 6.0]]])
+    a = oracle.aggregate(pb, L, C)
+    e = math.exp
+    # centre (1,0): weights from test_weights_hand_worked_two_rows
+    ws = [e(-1 / 4) * e(-1), 1.0, e(-1 / 4) * e(-1), e(-2 / 4), e(-1 / 4) * e(-1),
+          e(-2 / 4) * e(-4)]
+    cs = [1, 2, 3, 4, 5, 6]
+    want = sum(wi * ci for wi, ci in zip(ws, cs)) / sum(ws)
+    assert a[0, 0, 1] == pytest.approx(want, rel=1e-14)
+    # corner (0,1), L = 110: taps (0,0)=100,(1,0)=110,(0,1)=110 centre,(1,1)=100
+    ws = [e(-1 / 4) * e(-1), e(-2 / 4) * 1.0, 1.0, e(-1 / 4) * e(-1)]
+    cs = [1, 2, 4, 5]
+    want = sum(wi * ci for wi, ci in zip(ws, cs)) / sum(ws)
+    assert a[0, 1, 0] == pytest.approx(want, rel=1e-14)
+
+
+def _box_mean(vol, r):
+    """Mean over the in-image (2r+1)^2 window via integral images."""
+    D, H, W = vol.shape
+    out = np.empty_like(vol)
+    ones = np.ones((H, W))
+
+    def boxsum(img):
+        ii = np.zeros((H + 1, W + 1))
+        ii[1:, 1:] = img.cumsum(0).cumsum(1)
+        y0 = np.clip(np.arange(H) - r, 0, H)
+        y1 = np.clip(np.arange(H) + r + 1, 0, H)
+        x0 = np.clip(np.arange(W) - r, 0, W)
+        x1 = np.clip(np.arange(W) + r + 1, 0, W)
+        return (ii[y1][:, x1] - ii[y0][:, x1] - ii[y1][:, x0] + ii[y0][:, x0])
+
+    cnt = boxsum(ones)
+    for k in range(D):
+        out[k] = boxsum(vol[k]) / cnt
+    return out
+
+
+@pytest.mark.parametrize("channels", [1, 3])
+def test_uniform_weights_reduce_to_box_sad(channels):
+    """gamma_d = gamma_r = inf: FBS is box-filter SAD block matching."""
+    rng = _rng(21)
+    shape = (17, 29) if channels == 1 else (17, 29, 3)
+    L = rng.integers(0, 256, shape, dtype=np.uint8)
+    R = rng.integers(0, 256, shape, dtype=np.uint8)
+    pb = Problem(1, 8, 3, gamma_d=math.inf, gamma_r=math.inf, tau=40.0)
+    disp, sub, agg = oracle.fbs(pb, L, R, want_agg=True)
+    # textbook TAD through shifted slices, then integral-image box means
+    Lf = L.astype(np.float64).reshape(17, 29, -1)
+    Rf = R.astype(np.float64).reshape(17, 29, -1)
+    tad = np.empty((pb.n_disp, 17, 29))
+    for k, d in enumerate(range(pb.d_min, pb.d_max + 1)):
+        t = np.full((17, 29), 40.0)
+        t[:, d:] = np.minimum(np.abs(Lf[:, d:] - Rf[:, :29 - d]).mean(axis=2), 40.0)
+        tad[k] = t
+    box = _box_mean(tad, 3)
+    np.testing.assert_allclose(agg, box, rtol=1e-12, atol=1e-12)
+    # WTA on exact integer box sums of channels*TAD: the oracle's pick must attain
+    # the exact minimum; it must be the first minimiser wherever that is unique.
+    ints = np.rint(tad * channels).astype(np.int64)
+    ii = np.zeros((pb.n_disp, 18, 30), dtype=np.int64)
+    ii[:, 1:, 1:] = ints.cumsum(1).cumsum(2)
+    y0 = np.clip(np.arange(17) - 3, 0, 17); y1 = np.clip(np.arange(17) + 4, 0, 17)
+    x0 = np.clip(np.arange(29) - 3, 0, 29); x1 = np.clip(np.arange(29) + 4, 0, 29)
+    bs = (ii[:, y1][:, :, x1] - ii[:, y0][:, :, x1] - ii[:, y1][:, :, x0]
+          + ii[:, y0][:, :, x0])
+    picked = np.take_along_axis(bs, (disp - pb.d_min)[None].astype(np.int64), 0)[0]
+    assert np.all(picked == bs.min(axis=0))
+    unique = (bs == bs.min(axis=0)).sum(axis=0) == 1
+    np.testing.assert_array_equal(disp[unique], (np.argmin(bs, axis=0) + pb.d_min)[unique])
+
+
+def test_spatial_gaussian_is_normalised_convolution():
+    """gamma_r = inf: Eq. (6) is a normalised convolution with exp(-dist^2/gamma_d^2)."""
+    rng = _rng(22)
+    H, W = 14, 19
+    L = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    C = rng.uniform(0, 40, (3, H, W))
+    r, g = 3, 1.7
+    pb = Problem(0, 2, r, gamma_d=g, gamma_r=math.inf)
+    a = oracle.aggregate(pb, L, C)
+    ax = np.arange(-r, r + 1)
+    K = np.exp(-(ax[:, None] ** 2 + ax[None, :] ** 2) / g ** 2)
+    den = ndimage.correlate(np.ones((H, W)), K, mode="constant", cval=0.0)
+    for k in range(3):
+        num = ndimage.correlate(C[k], K, mode="constant", cval=0.0)
+        np.testing.assert_allclose(a[k], num / den, rtol=1e-12)
+
+
+def test_radius_zero_is_pixelwise_wta():
+    rng = _rng(23)
+    L = rng.integers(0, 256, (8, 21), dtype=np.uint8)
+    R = rng.integers(0, 256, (8, 21), dtype=np.uint8)
+    pb = Problem(0, 10, 0, gamma_d=3.0, gamma_r=9.0, tau=255.0)
+    disp, sub, agg = oracle.fbs(pb, L, R, want_agg=True)
+    c = oracle.cost(pb, L, R)
+    np.testing.assert_array_equal(agg, c)
+    np.testing.assert_array_equal(disp, np.argmin(c, axis=0))
+
+
+def test_tiny_gamma_r_keeps_only_equal_intensities():
+    """gamma_r -> 0: only taps with the centre's intensity keep weight."""
+    L = np.array([[5, 5, 9, 5, 9]], dtype=np.uint8)
+    C = np.array([[[1.0, 2.0, 100.0, 4.0, 100.0]]])
+    pb = Problem(0, 0, 2, gamma_d=math.inf, gamma_r=1e-3)
+    a = oracle.aggregate(pb, L, C)
+    assert a[0, 0, 1] == pytest.approx((1 + 2 + 4) / 3.0, rel=1e-14)
+    assert a[0, 0, 2] == pytest.approx(100.0, rel=1e-14)
+
+
+# --------------------------------------------------------- a5/a6: WTA and Eq. (10)
+
+
+@pytest.mark.parametrize("delta", [4.3, 7.0, 7.49, 2.51, 10.999])
+def test_subpixel_exact_on_quadratic(delta):
+    """Eq. (10) recovers the vertex of a parabola exactly."""
+    D = 16
+    d = np.arange(D, dtype=np.float64)
+    prof = 0.7 * (d - delta) ** 2 + 3.0
+    vol = np.repeat(prof[:, None, None], 16, axis=2)   # 1 x 16 image
+    pb = Problem(0, D - 1, 0, 1.0, 1.0)
+    disp, sub = oracle.wta_subpixel(pb, vol)
+    assert np.all(disp == round(delta))
+    np.testing.assert_allclose(sub, delta, rtol=0, atol=1e-12)
+    # invariance under A -> alpha*A + beta (alpha > 0)
+    disp2, sub2 = oracle.wta_subpixel(pb, 5.0 * vol - 2.0)
+    np.testing.assert_allclose(sub2, delta, atol=1e-12)
+
+
+def test_wta_first_minimum_and_edges():
+    D = 6
+    pb = Problem(3, 3 + D - 1, 0, 1.0, 1.0)
+    vols = {
+        "tie": [5.0, 2.0, 7.0, 2.0, 9.0, 9.0],     # -> first of the two minima, d=4
+        "low_edge": [1.0, 2.0, 3.0, 4.0, 5.0, 6.0],
+        "high_edge": [6.0, 5.0, 4.0, 3.0, 2.0, 1.0],
+        "flat": [4.0] * 6,
+    }
+    for name, prof in vols.items():
+        vol = np.repeat(np.array(prof)[:, None, None], 9, axis=2)
+        disp, sub = oracle.wta_subpixel(pb, vol)
+        if name == "tie":
+            assert disp[0, 0] == 4
+            # parabola through (3,5), (4,2), (5,7): vertex 4 + (5-7)/(10+14-8)
+            assert sub[0, 0] == pytest.approx(4 + (5 - 7) / (2 * 5 + 2 * 7 - 4 * 2), abs=1e-15)
+        elif name == "low_edge":
+            assert disp[0, 0] == 3 and sub[0, 0] == 3.0
+        elif name == "high_edge":
+            assert disp[0, 0] == 8 and sub[0, 0] == 8.0
+        else:
+            assert disp[0, 0] == 3 and sub[0, 0] == 3.0
+
+
+def test_subpixel_within_half_pixel():
+    rng = _rng(31)
+    vol = rng.uniform(0, 10, (12, 5, 30))
+    pb = Problem(0, 11, 0, 1.0, 1.0)
+    disp, sub = oracle.wta_subpixel(pb, vol)
+    assert np.all(np.abs(sub - disp) <= 0.5 + 1e-15)
+    np.testing.assert_array_equal(disp, np.argmin(vol, axis=0))
+
+
+# ------------------------------------------------------ whole pipeline, a1-a6
+
+
+@pytest.mark.parametrize("channels,cost_type", [(1, TAD), (3, TAD), (1, NCC)])
+def test_fronto_parallel_plane_exact_recovery(channels, cost_type):
+    """R(x,y) = L(x+d0,y): every pixel whose window sees only valid matches gets d0."""
+    d0, r = 5, 2
+    L, R = scenes.textured_fronto_pair(40, 18, d0, seed=41, channels=channels)
+    pb = Problem(0, 11, r, gamma_d=2.5, gamma_r=12.0, tau=40.0, cost_type=cost_type)
+    disp, sub = oracle.fbs(pb, L, R)
+    rr = 1 if cost_type == NCC else 0
+    x = np.arange(40)
+    ok = (x - r - rr >= d0) & (x + r + rr <= 39)
+    assert np.all(disp[:, ok] == d0)
+
+
+def test_gray_replicated_to_rgb_is_gray():
+    rng = _rng(51)
+    G = rng.integers(0, 256, (11, 25), dtype=np.uint8)
+    H_ = rng.integers(0, 256, (11, 25), dtype=np.uint8)
+    pb = Problem(0, 9, 2, gamma_d=2.0, gamma_r=10.0, tau=40.0)
+    d1, s1, a1 = oracle.fbs(pb, G, H_, want_agg=True)
+    d3, s3, a3 = oracle.fbs(pb, np.repeat(G[..., None], 3, 2), np.repeat(H_[..., None], 3, 2),
+                            want_agg=True)
+    np.testing.assert_array_equal(d1, d3)
+    np.testing.assert_allclose(a1, a3, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(s1, s3, rtol=0, atol=1e-13)
+
+
+def test_pipeline_is_composition_of_steps():
+    wl = scenes.workload("tiny")
+    p = scenes.make_pair(wl)
+    pb = Problem.from_workload(wl)
+    disp, sub, agg = oracle.fbs(pb, p.left, p.right, want_agg=True)
+    c = oracle.cost(pb, p.left, p.right)
+    a = oracle.aggregate(pb, p.left, c)
+    d2, s2 = oracle.wta_subpixel(pb, a)
+    np.testing.assert_array_equal(agg, a)
+    np.testing.assert_array_equal(disp, d2)
+    np.testing.assert_array_equal(sub, s2)
+
+
+@pytest.mark.parametrize("cost_type", [TAD, NCC])
+def test_per_pixel_entry_matches_volumes(cost_type):
+    wl = scenes.workload("tiny")
+    p = scenes.make_pair(wl)
+    pb = Problem.from_workload(wl, cost_type=cost_type)
+    disp, sub, agg = oracle.fbs(pb, p.left, p.right, want_agg=True)
+    ys, xs = np.mgrid[0:48:7, 0:64:5]
+    a, d, s = oracle.fbs_pixels(pb, p.left, p.right, xs.ravel(), ys.ravel())
+    np.testing.assert_allclose(a, agg[:, ys.ravel(), xs.ravel()].T, rtol=1e-13)
+    np.testing.assert_array_equal(d, disp[ys.ravel(), xs.ravel()])
+    np.testing.assert_allclose(s, sub[ys.ravel(), xs.ravel()], atol=1e-12)
+
+
+def _brute(pb, L, R):
+    """Eqs. (1)-(3), (6)-(8), (10) as literal loops (window recomputed per (p, d))."""
+    L = L.astype(np.float64).reshape(L.shape[0], L.shape[1], -1)
+    R = R.astype(np.float64).reshape(R.shape[0], R.shape[1], -1)
+    H, W, C = L.shape
+    r = pb.radius
+
+    def c_at(x, y, d):
+        if x - d < 0:
+            return pb.tau if pb.cost_type == TAD else 2.0
+        if pb.cost_type == TAD:
+            return min(sum(abs(L[y, x, ch] - R[y, x - d, ch]) for ch in range(C)) / C, pb.tau)
+        rr = pb.ncc_radius
+        bl = [L[min(max(j, 0), H - 1), min(max(i, 0), W - 1), 0]
+              for j in range(y - rr, y + rr + 1) for i in range(x - rr, x + rr + 1)]
+        br = [R[min(max(j, 0), H - 1), min(max(i - d, 0), W - 1), 0]
+              for j in range(y - rr, y + rr + 1) for i in range(x - rr, x + rr + 1)]
+        n = len(bl)
+        ml, mr = sum(bl) / n, sum(br) / n
+        sl = math.sqrt(max(sum(v * v for v in bl) / n - ml * ml, 0.0))
+        sr = math.sqrt(max(sum(v * v for v in br) / n - mr * mr, 0.0))
+        if sl == 0 or sr == 0:
+            return 1.0
+        return 1.0 - (sum(a * b for a, b in zip(bl, br)) - n * ml * mr) / (n * sl * sr)
+
+    disp = np.zeros((H, W), dtype=np.int32)
+    sub = np.zeros((H, W))
+    agg = np.zeros((pb.n_disp, H, W))
+    for y in range(H):
+        for x in range(W):
+            for k, d in enumerate(range(pb.d_min, pb.d_max + 1)):
+                num = den = 0.0
+                for j in range(y - r, y + r + 1):
+                    for i in range(x - r, x + r + 1):
+                        if not (0 <= i < W and 0 <= j < H):
+                            continue
+                        wd = math.exp(-((i - x) ** 2 + (j - y) ** 2) / pb.gamma_d ** 2)
+                        dI2 = sum((L[j, i, ch] - L[y, x, ch]) ** 2 for ch in range(C)) / C
+                        wr = math.exp(-dI2 / pb.gamma_r ** 2)
+                        num += wd * wr * c_at(i, j, d)
+                        den += wd * wr
+                agg[k, y, x] = num / den
+            prof = list(agg[:, y, x])
+            b = prof.index(min(prof))
+            ds = float(pb.d_min + b)
+            if 0 < b < len(prof) - 1:
+                cm, c0, cp = prof[b - 1], prof[b], prof[b + 1]
+                den = 2 * cm + 2 * cp - 4 * c0
+                if den > 0:
+                    ds += (cm - cp) / den
+            disp[y, x] = pb.d_min + b
+            sub[y, x] = ds
+    return disp, sub, agg
+
+
+@pytest.mark.parametrize("channels,cost_type,r", [(1, TAD, 2), (3, TAD, 1), (1, NCC, 2)])
+def test_brute_force_tiny(channels, cost_type, r):
+    rng = _rng(61 + channels + cost_type)
+    shape = (7, 12) if channels == 1 else (7, 12, 3)
+    L = rng.integers(0, 256, shape, dtype=np.uint8)
+    R = np.roll(L, -3, axis=1)
+    R = np.clip(R.astype(int) + rng.integers(-4, 5, shape), 0, 255).astype(np.uint8)
+    pb = Problem(1, 6, r, gamma_d=1.5, gamma_r=14.0, tau=30.0, cost_type=cost_type)
+    d0, s0, a0 = _brute(pb, L, R)
+    d1, s1, a1 = oracle.fbs(pb, L, R, want_agg=True)
+    np.testing.assert_allclose(a1, a0, rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(d1, d0)
+    np.testing.assert_allclose(s1, s0, atol=1e-11)
+
+
+def test_invalid_parameters_raise():
+    L = np.zeros((4, 8), dtype=np.uint8)
+    with pytest.raises(ValueError):
+        oracle.fbs(Problem(0, 8, 1, 1.0, 1.0), L, L)       # d_max >= width
+    with pytest.raises(ValueError):
+        oracle.fbs(Problem(0, 3, 1, 0.0, 1.0), L, L)       # gamma_d <= 0
+    with pytest.raises(ValueError):
+        oracle.fbs(Problem(0, 3, 1, 1.0, 1.0, cost_type=NCC),
+                   np.zeros((4, 8, 3), np.uint8), np.zeros((4, 8, 3), np.uint8))
