@@ -1,0 +1,241 @@
+// fbs_api.hip - the extern "C" entry points of include/fbs.h.
+//
+// Host side only: parameter validation (before anything is enqueued), the
+// weight tables of Eqs. 7-8 in double precision rounded once to float, the
+// choice of kernel, and error reporting.  No entry point allocates memory or
+// synchronises the stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "fbs_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fbs_status fail(fbs_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+fbs_status fail(fbs_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+fbs_status hip_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return FBS_OK;
+    return fail(FBS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool sigma_ok(float s) { return !isnan(s) && s > 0.0f; }
+
+// Full check of the parameters of the cost / aggregation / fused paths.
+fbs_status check_params(const fbs_params* p)
+{
+    if (!p) return fail(FBS_E_INVALID, "params is NULL");
+    if (p->width < 1 || p->height < 1) return fail(FBS_E_INVALID, "width/height must be >= 1");
+    if (p->width > 65535 || p->height > 65535)
+        return fail(FBS_E_UNSUPPORTED, "width/height above 65535");
+    if (p->channels != 1 && p->channels != 3) return fail(FBS_E_INVALID, "channels must be 1 or 3");
+    if ((long long)p->row_stride < (long long)p->width * p->channels)
+        return fail(FBS_E_INVALID, "row_stride %d < width*channels", p->row_stride);
+    if (p->d_min < 0 || p->d_max < p->d_min || p->d_max >= p->width)
+        return fail(FBS_E_INVALID, "need 0 <= d_min <= d_max < width (got %d..%d, width %d)",
+                    p->d_min, p->d_max, p->width);
+    if (p->d_max - p->d_min + 1 > FBS_MAX_DISP)
+        return fail(FBS_E_UNSUPPORTED, "more than %d disparities", FBS_MAX_DISP);
+    if (p->radius < 0) return fail(FBS_E_INVALID, "radius must be >= 0");
+    if (p->radius > FBS_MAX_RADIUS)
+        return fail(FBS_E_UNSUPPORTED, "radius %d above %d", p->radius, FBS_MAX_RADIUS);
+    if (!sigma_ok(p->sigma_s) || !sigma_ok(p->sigma_r))
+        return fail(FBS_E_INVALID, "sigma_s and sigma_r must be > 0");
+    if (p->cost_type == FBS_COST_TAD) {
+        if (isnan(p->cost_cap) || !(p->cost_cap > 0.0f))
+            return fail(FBS_E_INVALID, "cost_cap must be > 0");
+    } else if (p->cost_type == FBS_COST_NCC) {
+        if (p->channels != 1) return fail(FBS_E_UNSUPPORTED, "NCC cost needs channels == 1");
+        if (p->ncc_radius < 0 || p->ncc_radius > FBS_MAX_NCC_RADIUS)
+            return fail(FBS_E_UNSUPPORTED, "ncc_radius must be in 0..%d", FBS_MAX_NCC_RADIUS);
+    } else {
+        return fail(FBS_E_INVALID, "unknown cost_type %d", p->cost_type);
+    }
+    if (p->flags & ~FBS_F_FORCE_VALU) return fail(FBS_E_INVALID, "unknown flags 0x%x", p->flags);
+    return FBS_OK;
+}
+
+fbs::Geom make_geom(const fbs_params* p)
+{
+    fbs::Geom g;
+    g.W = p->width;
+    g.H = p->height;
+    g.C = p->channels;
+    g.stride = p->row_stride;
+    g.dmin = p->d_min;
+    g.D = p->d_max - p->d_min + 1;
+    g.r = p->radius;
+    g.tau = p->cost_cap;
+    g.ncc_r = p->ncc_radius;
+    return g;
+}
+
+// Eqs. 7-8 factor tables, in double precision, rounded once to float.
+fbs::Tables make_tables(const fbs_params* p)
+{
+    fbs::Tables t;
+    const double gd = (double)p->sigma_s, gr = (double)p->sigma_r;
+    for (int k = 0; k <= FBS_MAX_RADIUS; ++k) t.gs[k] = (float)exp(-(double)(k * k) / (gd * gd));
+    const double scale = (p->channels == 3) ? 3.0 : 1.0;
+    for (int i = 0; i < 256; ++i) t.gr[i] = (float)exp(-(double)(i * i) / (scale * gr * gr));
+    return t;
+}
+
+size_t ncc_ws_bytes(const fbs_params* p)
+{
+    const size_t b = (size_t)16 * p->width * p->height;
+    return (b + 255) & ~(size_t)255;
+}
+
+bool aligned4(const void* q) { return ((uintptr_t)q & 3u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+fbs_status fbs_validate(const fbs_params* p) { return check_params(p); }
+
+fbs_status fbs_workspace_bytes(const fbs_params* p, size_t* bytes)
+{
+    fbs_status st = check_params(p);
+    if (st != FBS_OK) return st;
+    if (!bytes) return fail(FBS_E_INVALID, "bytes is NULL");
+    *bytes = p->cost_type == FBS_COST_NCC ? ncc_ws_bytes(p) : 0;
+    return FBS_OK;
+}
+
+fbs_status fbs_cost(const fbs_params* p, const uint8_t* left, const uint8_t* right, float* cost,
+                    void* workspace, void* stream)
+{
+    fbs_status st = check_params(p);
+    if (st != FBS_OK) return st;
+    if (!left || !right || !cost) return fail(FBS_E_INVALID, "left, right and cost are required");
+    if (!aligned4(cost)) return fail(FBS_E_INVALID, "cost must be 4-byte aligned");
+    if (p->cost_type == FBS_COST_NCC && !workspace)
+        return fail(FBS_E_WORKSPACE, "NCC cost needs %zu bytes of workspace", ncc_ws_bytes(p));
+    if (workspace && ((uintptr_t)workspace & 15u))
+        return fail(FBS_E_INVALID, "workspace must be 16-byte aligned");
+    const fbs::Geom g = make_geom(p);
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    if (p->cost_type == FBS_COST_TAD) return hip_status(fbs::launch_cost_tad(g, left, right, cost, s), "fbs_cost");
+    int2* stats = (int2*)workspace;
+    st = hip_status(fbs::launch_ncc_stats(g, left, right, stats, s), "fbs_cost(stats)");
+    if (st != FBS_OK) return st;
+    return hip_status(fbs::launch_cost_ncc(g, left, right, stats, cost, s), "fbs_cost(ncc)");
+}
+
+fbs_status fbs_aggregate(const fbs_params* p, const uint8_t* left, const float* cost, float* agg,
+                         void* stream)
+{
+    fbs_status st = check_params(p);
+    if (st != FBS_OK) return st;
+    if (!left || !cost || !agg) return fail(FBS_E_INVALID, "left, cost and agg are required");
+    if (!aligned4(cost) || !aligned4(agg)) return fail(FBS_E_INVALID, "volumes must be 4-byte aligned");
+    const fbs::Geom g = make_geom(p);
+    const size_t vol = (size_t)g.W * g.H * g.D * sizeof(float);
+    if ((const char*)cost < (const char*)agg + vol && (const char*)agg < (const char*)cost + vol)
+        return fail(FBS_E_INVALID, "cost and agg overlap");
+    const fbs::Tables t = make_tables(p);
+    (void)hipGetLastError();
+    return hip_status(fbs::launch_valu(g, t, fbs::SRC_VOLUME, left, nullptr, cost, nullptr, agg,
+                                       nullptr, nullptr, (hipStream_t)stream),
+                      "fbs_aggregate");
+}
+
+fbs_status fbs_wta_subpixel(const fbs_params* p, const float* agg, int32_t* disp, float* disp_sub,
+                            void* stream)
+{
+    if (!p) return fail(FBS_E_INVALID, "params is NULL");
+    if (p->width < 1 || p->height < 1) return fail(FBS_E_INVALID, "width/height must be >= 1");
+    if (p->width > 65535 || p->height > 65535)
+        return fail(FBS_E_UNSUPPORTED, "width/height above 65535");
+    if (p->d_min < 0 || p->d_max < p->d_min)
+        return fail(FBS_E_INVALID, "need 0 <= d_min <= d_max");
+    if (p->d_max - p->d_min + 1 > FBS_MAX_DISP)
+        return fail(FBS_E_UNSUPPORTED, "more than %d disparities", FBS_MAX_DISP);
+    if (!agg) return fail(FBS_E_INVALID, "agg is required");
+    if (!aligned4(agg) || !aligned4(disp) || !aligned4(disp_sub))
+        return fail(FBS_E_INVALID, "pointers must be 4-byte aligned");
+    if (!disp && !disp_sub) return FBS_OK;
+    fbs::Geom g = make_geom(p);
+    (void)hipGetLastError();
+    return hip_status(fbs::launch_wta_subpixel(g, agg, disp, disp_sub, (hipStream_t)stream),
+                      "fbs_wta_subpixel");
+}
+
+int fbs_run_variant(const fbs_params* p)
+{
+    fbs_status st = check_params(p);
+    if (st != FBS_OK) return st;
+    if (p->cost_type != FBS_COST_TAD || (p->flags & FBS_F_FORCE_VALU)) return 0;
+    return fbs::mfma_supported(make_geom(p)) ? 1 : 0;
+}
+
+fbs_status fbs_run(const fbs_params* p, const uint8_t* left, const uint8_t* right, int32_t* disp,
+                   float* disp_sub, float* agg_out, void* workspace, void* stream)
+{
+    fbs_status st = check_params(p);
+    if (st != FBS_OK) return st;
+    if (!left || !right) return fail(FBS_E_INVALID, "left and right are required");
+    if (!aligned4(disp) || !aligned4(disp_sub) || !aligned4(agg_out))
+        return fail(FBS_E_INVALID, "outputs must be 4-byte aligned");
+    if (p->cost_type == FBS_COST_NCC && !workspace)
+        return fail(FBS_E_WORKSPACE, "NCC cost needs %zu bytes of workspace", ncc_ws_bytes(p));
+    if (workspace && ((uintptr_t)workspace & 15u))
+        return fail(FBS_E_INVALID, "workspace must be 16-byte aligned");
+    if (!disp && !disp_sub && !agg_out) return FBS_OK;
+    const fbs::Geom g = make_geom(p);
+    const fbs::Tables t = make_tables(p);
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    if (p->cost_type == FBS_COST_NCC) {
+        int2* stats = (int2*)workspace;
+        st = hip_status(fbs::launch_ncc_stats(g, left, right, stats, s), "fbs_run(stats)");
+        if (st != FBS_OK) return st;
+        return hip_status(fbs::launch_valu(g, t, fbs::SRC_NCC, left, right, nullptr, stats, agg_out,
+                                           disp, disp_sub, s),
+                          "fbs_run(ncc)");
+    }
+    if (!(p->flags & FBS_F_FORCE_VALU) && fbs::mfma_supported(g))
+        return hip_status(fbs::launch_mfma(g, t, left, right, disp, disp_sub, agg_out, s),
+                          "fbs_run(mfma)");
+    return hip_status(fbs::launch_valu(g, t, fbs::SRC_TAD, left, right, nullptr, nullptr, agg_out,
+                                       disp, disp_sub, s),
+                      "fbs_run(valu)");
+}
+
+const char* fbs_status_str(int status)
+{
+    switch (status) {
+    case FBS_OK: return "ok";
+    case FBS_E_INVALID: return "invalid argument";
+    case FBS_E_UNSUPPORTED: return "unsupported";
+    case FBS_E_HIP: return "HIP error";
+    case FBS_E_WORKSPACE: return "workspace missing";
+    default: return "unknown status";
+    }
+}
+
+const char* fbs_last_error(void) { return g_last_error.c_str(); }
+
+const char* fbs_version(void) { return "0.1.0"; }
+
+}  // extern "C"

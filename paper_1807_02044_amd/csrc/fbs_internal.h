@@ -1,0 +1,59 @@
+// fbs_internal.h - types shared by the HIP kernels and the C-ABI layer.
+//
+// Everything here is device-side plumbing for the gfx950 kernels; the public
+// contract is include/fbs.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fbs.h"
+
+namespace fbs {
+
+// Problem geometry, passed to kernels by value.
+struct Geom {
+    int W, H, C;      // image size and channel count (1 or 3)
+    int stride;       // bytes between image rows
+    int dmin, D;      // first disparity and number of disparities
+    int r;            // aggregation radius rho
+    float tau;        // TAD cap
+    int ncc_r;        // NCC block radius varrho
+};
+
+// Support-weight factors, computed on the host in double precision and
+// rounded once to float (Eqs. 7-8):
+//   gs[k] = exp(-k^2 / gamma_d^2)            k = |dx| or |dy|
+//   gr[i] = exp(-i^2 / gamma_r^2)            gray, i = |I(q) - I(p)|
+//   gr[i] = exp(-i^2 / (3 gamma_r^2))        RGB, one factor per channel
+// so that w = gs[|dx|] * gs[|dy|] * prod_ch gr[|dI_ch|].
+struct Tables {
+    float gs[FBS_MAX_RADIUS + 1];
+    float gr[256];
+};
+
+enum CostSrc { SRC_VOLUME = 0, SRC_TAD = 1, SRC_NCC = 2 };
+
+// ---- launchers (each returns the launch status; no synchronisation) ----
+hipError_t launch_cost_tad(const Geom& g, const uint8_t* L, const uint8_t* R, float* cost,
+                           hipStream_t s);
+hipError_t launch_ncc_stats(const Geom& g, const uint8_t* L, const uint8_t* R, int2* stats,
+                            hipStream_t s);
+hipError_t launch_cost_ncc(const Geom& g, const uint8_t* L, const uint8_t* R,
+                           const int2* stats, float* cost, hipStream_t s);
+hipError_t launch_wta_subpixel(const Geom& g, const float* agg, int32_t* disp, float* sub,
+                               hipStream_t s);
+
+// Bilateral aggregation on the vector ALUs.  src selects where costs come
+// from (a materialised volume, or TAD / NCC computed in the kernel); agg,
+// disp and sub are each optional.
+hipError_t launch_valu(const Geom& g, const Tables& t, CostSrc src, const uint8_t* L,
+                       const uint8_t* R, const float* cost, const int2* stats, float* agg,
+                       int32_t* disp, float* sub, hipStream_t s);
+
+// Fused TAD path on the matrix cores.
+bool mfma_supported(const Geom& g);
+hipError_t launch_mfma(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
+                       int32_t* disp, float* sub, float* agg, hipStream_t s);
+
+}  // namespace fbs

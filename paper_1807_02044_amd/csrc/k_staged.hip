@@ -1,0 +1,173 @@
+// k_staged.hip - the materialising kernels of the staged path:
+//   cost volume (TAD, or the paper's NCC with pre-computed block sums) and
+//   WTA + subpixel over an aggregated volume.
+//
+// All of them are bound by HBM traffic: each writes or reads 4*W*H*D bytes of
+// float volume once, with lanes along x so every access is a coalesced row
+// segment of the [D][H][W] layout.
+#include "fbs_device.h"
+#include "fbs_internal.h"
+
+namespace fbs {
+
+namespace {
+
+constexpr int kRowThreads = 256;  // lanes along x per workgroup
+constexpr int kSlab = 16;         // disparities per thread in the cost kernels
+
+// TAD cost (Section II-A cost step with the truncated absolute difference):
+// C(x,y,d) = min(mean_ch |L - R(x-d)|, tau); tau where x-d is off-image.
+template <int CH>
+__global__ __launch_bounds__(kRowThreads) void k_cost_tad(Geom g, const uint8_t* __restrict__ L,
+                                                          const uint8_t* __restrict__ R,
+                                                          float* __restrict__ cost)
+{
+    const int x = blockIdx.x * kRowThreads + threadIdx.x;
+    const int y = blockIdx.y;
+    const int k0 = blockIdx.z * kSlab;
+    if (x >= g.W) return;
+    const uint8_t* lrow = L + (size_t)y * g.stride;
+    const uint8_t* rrow = R + (size_t)y * g.stride;
+    int lv[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) lv[c] = lrow[x * CH + c];
+    const size_t plane = (size_t)g.W * g.H;
+    float* out = cost + (size_t)y * g.W + x;
+    const int kend = min(k0 + kSlab, g.D);
+    for (int k = k0; k < kend; ++k) {
+        const int xr = x - (g.dmin + k);
+        float c = g.tau;
+        if (xr >= 0) {
+            int s = 0;
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch) s += abs(lv[ch] - (int)rrow[xr * CH + ch]);
+            const float m = (CH == 1) ? (float)s : (float)s / 3.0f;
+            c = fminf(m, g.tau);
+        }
+        out[(size_t)k * plane] = c;
+    }
+}
+
+// Per-pixel block sums S = sum i and S2 = sum i^2 over the clamp-to-edge
+// (2*varrho+1)^2 block: the mean / deviation pre-computation of Section III.
+// stats[0] holds the left image, stats[1] the right image, as [H][W] int2.
+__global__ __launch_bounds__(kRowThreads) void k_ncc_stats(Geom g, const uint8_t* __restrict__ L,
+                                                           const uint8_t* __restrict__ R,
+                                                           int2* __restrict__ stats)
+{
+    const int x = blockIdx.x * kRowThreads + threadIdx.x;
+    const int y = blockIdx.y;
+    const int which = blockIdx.z;
+    if (x >= g.W) return;
+    const uint8_t* img = which ? R : L;
+    int s = 0, s2 = 0;
+    for (int j = -g.ncc_r; j <= g.ncc_r; ++j) {
+        const int yy = min(max(y + j, 0), g.H - 1);
+        const uint8_t* row = img + (size_t)yy * g.stride;
+        for (int i = -g.ncc_r; i <= g.ncc_r; ++i) {
+            const int v = row[min(max(x + i, 0), g.W - 1)];
+            s += v;
+            s2 += v * v;
+        }
+    }
+    stats[(size_t)which * g.W * g.H + (size_t)y * g.W + x] = make_int2(s, s2);
+}
+
+// NCC cost 1 - c (Eq. 1): only the cross term sum i_l * i_r is formed here;
+// the block sums come from k_ncc_stats.
+__global__ __launch_bounds__(kRowThreads) void k_cost_ncc(Geom g, const uint8_t* __restrict__ L,
+                                                          const uint8_t* __restrict__ R,
+                                                          const int2* __restrict__ stats,
+                                                          float* __restrict__ cost)
+{
+    const int x = blockIdx.x * kRowThreads + threadIdx.x;
+    const int y = blockIdx.y;
+    const int k0 = blockIdx.z * kSlab;
+    if (x >= g.W) return;
+    const size_t plane = (size_t)g.W * g.H;
+    const int n = (2 * g.ncc_r + 1) * (2 * g.ncc_r + 1);
+    const int2 sl = stats[(size_t)y * g.W + x];
+    float* out = cost + (size_t)y * g.W + x;
+    const int kend = min(k0 + kSlab, g.D);
+    for (int k = k0; k < kend; ++k) {
+        const int d = g.dmin + k;
+        float c = 2.0f;
+        if (x - d >= 0) {
+            int slr = 0;
+            for (int j = -g.ncc_r; j <= g.ncc_r; ++j) {
+                const int yy = min(max(y + j, 0), g.H - 1);
+                const uint8_t* lrow = L + (size_t)yy * g.stride;
+                const uint8_t* rrow = R + (size_t)yy * g.stride;
+                for (int i = -g.ncc_r; i <= g.ncc_r; ++i) {
+                    const int xl = min(max(x + i, 0), g.W - 1);
+                    const int xr = min(max(x + i - d, 0), g.W - 1);
+                    slr += (int)lrow[xl] * (int)rrow[xr];
+                }
+            }
+            const int2 sr = stats[plane + (size_t)y * g.W + (x - d)];
+            c = ncc_cost(n, sl.x, sl.y, sr.x, sr.y, slr);
+        }
+        out[(size_t)k * plane] = c;
+    }
+}
+
+// WTA (Section II-C) and Eq. 10 over a materialised aggregated volume; one
+// lane per pixel, reading the D planes in order.
+__global__ __launch_bounds__(kRowThreads) void k_wta_subpixel(Geom g,
+                                                              const float* __restrict__ agg,
+                                                              int32_t* __restrict__ disp,
+                                                              float* __restrict__ sub)
+{
+    const int x = blockIdx.x * kRowThreads + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= g.W) return;
+    const size_t plane = (size_t)g.W * g.H;
+    const float* a = agg + (size_t)y * g.W + x;
+    Wta w;
+    w.init();
+    for (int k = 0; k < g.D; ++k) w.push(a[(size_t)k * plane], k);
+    int32_t d;
+    float ds;
+    w.finish(g.dmin, g.D, &d, &ds);
+    if (disp) disp[(size_t)y * g.W + x] = d;
+    if (sub) sub[(size_t)y * g.W + x] = ds;
+}
+
+}  // namespace
+
+hipError_t launch_cost_tad(const Geom& g, const uint8_t* L, const uint8_t* R, float* cost,
+                           hipStream_t s)
+{
+    dim3 grid((g.W + kRowThreads - 1) / kRowThreads, g.H, (g.D + kSlab - 1) / kSlab);
+    if (g.C == 3)
+        hipLaunchKernelGGL(k_cost_tad<3>, grid, dim3(kRowThreads), 0, s, g, L, R, cost);
+    else
+        hipLaunchKernelGGL(k_cost_tad<1>, grid, dim3(kRowThreads), 0, s, g, L, R, cost);
+    return hipGetLastError();
+}
+
+hipError_t launch_ncc_stats(const Geom& g, const uint8_t* L, const uint8_t* R, int2* stats,
+                            hipStream_t s)
+{
+    dim3 grid((g.W + kRowThreads - 1) / kRowThreads, g.H, 2);
+    hipLaunchKernelGGL(k_ncc_stats, grid, dim3(kRowThreads), 0, s, g, L, R, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_ncc(const Geom& g, const uint8_t* L, const uint8_t* R,
+                           const int2* stats, float* cost, hipStream_t s)
+{
+    dim3 grid((g.W + kRowThreads - 1) / kRowThreads, g.H, (g.D + kSlab - 1) / kSlab);
+    hipLaunchKernelGGL(k_cost_ncc, grid, dim3(kRowThreads), 0, s, g, L, R, stats, cost);
+    return hipGetLastError();
+}
+
+hipError_t launch_wta_subpixel(const Geom& g, const float* agg, int32_t* disp, float* sub,
+                               hipStream_t s)
+{
+    dim3 grid((g.W + kRowThreads - 1) / kRowThreads, g.H);
+    hipLaunchKernelGGL(k_wta_subpixel, grid, dim3(kRowThreads), 0, s, g, agg, disp, sub);
+    return hipGetLastError();
+}
+
+}  // namespace fbs
