@@ -85,7 +85,7 @@ typedef struct fbs_params {
     int32_t radius;     /* rho of Eq. 6, 0 <= radius <= FBS_MAX_RADIUS */
     float sigma_s;      /* gamma_d of Eq. 7, > 0 (+INFINITY allowed) */
     float sigma_r;      /* gamma_r of Eq. 8, > 0 (+INFINITY allowed) */
-    float cost_cap;     /* tau of the TAD cost, > 0 (TAD only) */
+    float cost_cap;     /* tau of the TAD cost, finite and > 0 (TAD only) */
     int32_t cost_type;  /* fbs_cost_type */
     int32_t ncc_radius; /* varrho of Eq. 1, 0..FBS_MAX_NCC_RADIUS (NCC only) */
     uint32_t flags;     /* FBS_F_* */

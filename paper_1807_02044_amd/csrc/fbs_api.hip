@@ -59,8 +59,8 @@ fbs_status check_params(const fbs_params* p)
     if (!sigma_ok(p->sigma_s) || !sigma_ok(p->sigma_r))
         return fail(FBS_E_INVALID, "sigma_s and sigma_r must be > 0");
     if (p->cost_type == FBS_COST_TAD) {
-        if (isnan(p->cost_cap) || !(p->cost_cap > 0.0f))
-            return fail(FBS_E_INVALID, "cost_cap must be > 0");
+        if (!isfinite(p->cost_cap) || !(p->cost_cap > 0.0f))
+            return fail(FBS_E_INVALID, "cost_cap must be finite and > 0");
     } else if (p->cost_type == FBS_COST_NCC) {
         if (p->channels != 1) return fail(FBS_E_UNSUPPORTED, "NCC cost needs channels == 1");
         if (p->ncc_radius < 0 || p->ncc_radius > FBS_MAX_NCC_RADIUS)

@@ -3,15 +3,19 @@
 * aggregated costs: |A_gpu - A_oracle| <= 1e-4 * |A_oracle| + 1e-6
   (the absolute floor only matters where the oracle's cost is 0);
 * integer disparity: equal, or the GPU's pick lies in the oracle's tie zone,
-  A_o(d_gpu) - A_o(d_o) <= 1e-5 * max(|A_o(d_gpu)|, |A_o(d_o)|) + 1e-30.
-  The absolute 1e-30 is the float32 range limit: a support weight below the
-  smallest normal float (2^-126) cannot be held by the kernel, so costs that
-  differ by less than T * tau * 2^-126 (< 4e-33 for every window and cap the
-  library accepts) are indistinguishable in float32;
+  A_o(d_gpu) - A_o(d_o) <= 1e-5 * max(|A_o(d_gpu)|, |A_o(d_o)|) + floor.
+  The absolute floor is the range limit of the kernels' weights.  The
+  matrix-core kernel holds each weight w <= 1 as fp16 hi + lo of w * 2^14,
+  and fp16's smallest subnormal is 2^-24, so weights below 2^-38 are zero
+  there and each weight carries an absolute error below 2^-38; Eq. 6 then
+  moves by at most T * c_max * 2^-38 (T taps, costs <= c_max, weight sum >= 1
+  from the centre tap), and two costs closer than twice that cannot be told
+  apart.  For the float32 vector kernel the same bound with 2^-126 is smaller
+  still.  floor = weight_floor(T, c_max) = 2 * T * c_max * 2^-38;
 * subpixel disparity: where the integers agree, |ds_gpu - ds_oracle| <= 1e-3.
   Eq. 10 amplifies cost errors by about 2 eps / (a + b), with
   a = A(d*-1) - A(d*) and b = A(d*+1) - A(d*), so a pixel whose parabola is
-  flat, (a + b) < 4e-3 * A(d*) (+ the float32-range floor), may miss; every such violator is counted and
+  flat, (a + b) < 4e-3 * A(d*) + 2000 * floor, may miss; every such violator is counted and
   returned, and a violator outside that zone fails.
 """
 from __future__ import annotations
@@ -25,6 +29,11 @@ AGG_RTOL = 1e-4
 AGG_ATOL = 1e-6
 TIE_RTOL = 1e-5
 TIE_ATOL = 1e-30
+
+
+def weight_floor(taps: int, c_max: float) -> float:
+    """Absolute resolution of the aggregated cost (see the module docstring)."""
+    return 2.0 * taps * c_max * 2.0 ** -38 + TIE_ATOL
 SUB_ATOL = 1e-3
 FLAT_ZONE = 4e-3
 
@@ -52,11 +61,12 @@ class Report:
                 + "; ".join(self.notes[:5]))
 
 
-def compare_agg(agg_gpu: np.ndarray, agg_o: np.ndarray, rep: Report) -> Report:
+def compare_agg(agg_gpu: np.ndarray, agg_o: np.ndarray, rep: Report,
+                floor: float = 0.0) -> Report:
     g = np.asarray(agg_gpu, dtype=np.float64)
     o = np.asarray(agg_o, dtype=np.float64)
     err = np.abs(g - o)
-    bad = err > AGG_RTOL * np.abs(o) + AGG_ATOL
+    bad = err > AGG_RTOL * np.abs(o) + max(AGG_ATOL, floor)
     rep.agg_bad += int(bad.sum())
     with np.errstate(divide="ignore", invalid="ignore"):
         rel = np.where(np.abs(o) > 0, err / np.abs(o), err)
@@ -68,7 +78,7 @@ def compare_agg(agg_gpu: np.ndarray, agg_o: np.ndarray, rep: Report) -> Report:
 
 
 def compare_maps(disp_gpu, sub_gpu, disp_o, sub_o, agg_o_pd: np.ndarray, d_min: int,
-                 rep: Report = None) -> Report:
+                 rep: Report = None, floor: float = TIE_ATOL) -> Report:
     """agg_o_pd: oracle aggregated costs as [D][n] for the n compared pixels."""
     rep = rep or Report()
     dg = np.asarray(disp_gpu).ravel().astype(np.int64)
@@ -87,7 +97,7 @@ def compare_maps(disp_gpu, sub_gpu, disp_o, sub_o, agg_o_pd: np.ndarray, d_min: 
     ag = A[dg - d_min, idx]
     ao = A[do - d_min, idx]
     eq = dg == do
-    tie = (~eq) & (ag - ao <= TIE_RTOL * np.maximum(np.abs(ag), np.abs(ao)) + TIE_ATOL)
+    tie = (~eq) & (ag - ao <= TIE_RTOL * np.maximum(np.abs(ag), np.abs(ao)) + floor)
     bad = (~eq) & (~tie)
     rep.disp_equal += int(eq.sum())
     rep.disp_tie += int(tie.sum())
@@ -106,8 +116,8 @@ def compare_maps(disp_gpu, sub_gpu, disp_o, sub_o, agg_o_pd: np.ndarray, d_min: 
         c0 = A[k, idx]
         a = A[km, idx] - c0
         b = A[kp, idx] - c0
-        # float32-range floor as for ties: 2 * eps / (a + b) with eps ~ 1e-30
-        flat = (a + b) < FLAT_ZONE * np.abs(c0) + 2e3 * TIE_ATOL
+        # with the absolute floor as cost error, 2 * eps / (a + b) > 1e-3 px
+        flat = (a + b) < FLAT_ZONE * np.abs(c0) + 2e3 * floor
         rep.sub_flat += int((viol & flat).sum())
         hard = viol & ~flat
         rep.sub_bad += int(hard.sum())

@@ -18,7 +18,7 @@ from paper_1807_02044_amd import _lib as L
 from paper_1807_02044_amd import scenes
 import paper_1807_02044_amd as fbs
 
-from parity import Report, compare_agg, compare_maps
+from parity import Report, compare_agg, compare_maps, weight_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -60,11 +60,16 @@ def _staged(p, Ld, Rd):
     return c, a, d, s
 
 
+def _floor(pb: Problem) -> float:
+    return weight_floor((2 * pb.radius + 1) ** 2, pb.tau if pb.cost_type == TAD else 2.0)
+
+
 def _full_compare(pb, left, right, disp, sub, agg=None):
     do, so, ao = oracle.fbs(pb, left, right, want_agg=True)
-    rep = compare_maps(disp, sub, do, so, ao.reshape(ao.shape[0], -1), pb.d_min)
+    fl = _floor(pb)
+    rep = compare_maps(disp, sub, do, so, ao.reshape(ao.shape[0], -1), pb.d_min, floor=fl)
     if agg is not None:
-        compare_agg(agg, ao, rep)
+        compare_agg(agg, ao, rep, floor=fl)
     return rep
 
 
@@ -225,8 +230,8 @@ def test_large_rgb_sampled_vs_oracle(force_valu):
     a_smp = _h(a_smp)
     del a
     ao, do, so = oracle.fbs_pixels(pb, pr.left, pr.right, xs, ys)
-    rep = compare_maps(d[ys, xs], s[ys, xs], do, so, ao.T, pb.d_min)
-    compare_agg(a_smp, ao.T, rep)
+    rep = compare_maps(d[ys, xs], s[ys, xs], do, so, ao.T, pb.d_min, floor=_floor(pb))
+    compare_agg(a_smp, ao.T, rep, floor=_floor(pb))
     _say(rep)
     assert rep.ok, str(rep)
 
