@@ -14,6 +14,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -38,7 +39,178 @@ def parse():
     ap.add_argument("--force-valu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-pair batched-plan comparison")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the learned-surrogate comparison")
+    ap.add_argument("--surrogate-frames", type=int, default=16)
+    ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(),
+                                                          "fbs_tune_gfx950.json"))
     return ap.parse_args()
+
+
+def _gen_pair(wl):
+    from paper_1807_02044_amd import scenes
+    p = scenes.make_pair(wl)
+    return p.left, p.right
+
+
+def batched(args, dev):
+    """64 uneven pairs: one graph launch of a tuned plan vs 64 fbs_run calls."""
+    import concurrent.futures as cf
+
+    import torch
+    from paper_1807_02044_amd import _lib as L
+    from paper_1807_02044_amd import scenes
+    import paper_1807_02044_amd as fbs
+
+    wls = scenes.batched_workloads()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(workers) as ex:
+        imgs = list(ex.map(_gen_pair, wls))
+    gen_s = time.perf_counter() - t0
+    params = [fbs.params_for(wl) for wl in wls]
+    Ls = [torch.from_numpy(a).to(dev) for a, _ in imgs]
+    Rs = [torch.from_numpy(b).to(dev) for _, b in imgs]
+    Ds = [torch.empty((w.height, w.width), dtype=torch.int32, device=dev) for w in wls]
+    Ss = [torch.empty((w.height, w.width), dtype=torch.float32, device=dev) for w in wls]
+    t0 = time.perf_counter()
+    plan = L.FbsPlan(params, tune_cache=args.tune_cache, tune=True)
+    plan_s = time.perf_counter() - t0
+    stream = torch.cuda.Stream(device=dev)
+    taps = sum(w.work_taps for w in wls)
+
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            fn()
+            stream.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.batch_steps):
+                fn()
+            e1.record(stream)
+            stream.synchronize()
+        return e0.elapsed_time(e1) / args.batch_steps
+
+    def graph():
+        plan.launch(Ls, Rs, Ds, Ss, stream)
+
+    def sequential():
+        for i in range(len(wls)):
+            L.fbs_run(params[i], Ls[i], Rs[i], Ds[i], Ss[i], None, None, stream)
+
+    ms_graph = timed(graph)
+    ms_seq = timed(sequential)
+    cfgs = [plan.pair_config(i) for i in range(len(wls))]
+    launches = plan.num_launches()
+    plan.close()
+    n = len(wls)
+    return {
+        "pairs": n, "taps": taps, "megapixels": sum(w.width * w.height for w in wls) / 1e6,
+        "graph_ms": ms_graph, "sequential_ms": ms_seq,
+        "frames_per_s_graph": n / (ms_graph * 1e-3),
+        "frames_per_s_sequential": n / (ms_seq * 1e-3),
+        "gpix_disp_tap_per_s_graph": taps / (ms_graph * 1e-3) / 1e9,
+        "gpix_disp_tap_per_s_sequential": taps / (ms_seq * 1e-3) / 1e9,
+        "speedup": ms_seq / ms_graph, "host_launches_graph": launches,
+        "host_launches_sequential": n,
+        "waves_per_wg": sorted({c[1] for c in cfgs}), "slab_blocks": sorted({c[2] for c in cfgs}),
+        "scene_gen_s": gen_s, "plan_create_s": plan_s,
+        "scenes": "64 seeded slanted-plane pairs, sizes/ranges/radii drawn per pair",
+    }
+
+
+def surrogate(args, dev):
+    """Plain full-radius FBS vs the learned surrogate (cheap run + net + gate)
+    on held-out 640x480, 96-disparity pairs; quality against the plain run."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+    from paper_1807_02044_amd import _lib as L
+    from paper_1807_02044_amd import surrogate as SG
+    import paper_1807_02044_amd as fbs
+
+    if not os.path.exists(SG.WEIGHTS):
+        return {"skipped": "no trained weights"}
+    summary = json.load(open(SG.SUMMARY)) if os.path.exists(SG.SUMMARY) else {}
+    calib = summary.get("gate_calibrated", {}).get("gate_frac")
+    seeds = [SG.EVAL_SEED0 + 100 + i for i in range(args.surrogate_frames)]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(workers) as ex:
+        imgs = list(ex.map(SG._gen, seeds))
+    cw, fw = SG.workloads(seeds[0])
+    pc, pf = fbs.params_for(cw), fbs.params_for(fw)
+    W, H, D = cw.width, cw.height, cw.n_disp
+    Ls = [torch.from_numpy(a).to(dev) for a, _ in imgs]
+    Rs = [torch.from_numpy(b).to(dev) for _, b in imgs]
+    sur = L.FbsSurrogate(W, H, D)
+    sur.set_params(np.load(SG.WEIGHTS))
+    stream = torch.cuda.Stream(device=dev)
+    n = len(seeds)
+    plain = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(n)]
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    vol = torch.empty((D, H, W), dtype=torch.float32, device=dev)
+    cheap = torch.empty((H, W), dtype=torch.float32, device=dev)
+    feat = torch.empty((H, W, 32), dtype=torch.int16, device=dev)
+
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            for i in range(n):
+                fn(i)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for i in range(n):
+                fn(i)
+            stream.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    def run_plain(i):
+        L.fbs_run(pf, Ls[i], Rs[i], None, plain[i], None, None, stream)
+
+    def run_net(i):
+        L.fbs_run(pc, Ls[i], Rs[i], None, cheap, vol, None, stream)
+        sur.features(pc, Ls[i], vol, feat, stream)
+        sur.forward(W, H, feat, cheap, out, stream)
+
+    fb = {}
+
+    def run_gated(frac):
+        def f(i):
+            fb[i] = sur.run(pc, pf, Ls[i], Rs[i], out, 1.0, frac, stream)
+        return f
+
+    t_plain = timed(run_plain)
+    t_net = timed(run_net)
+    bad, mae = [], []
+    with torch.cuda.stream(stream):
+        for i in range(n):
+            run_net(i)
+            e = (out - plain[i]).abs()
+            bad.append(float((e > 1.0).float().mean().item()))
+            mae.append(float(e.mean().item()))
+    res = {
+        "frames": n, "workload": f"{W}x{H} gray, d {cw.d_min}..{cw.d_max}, "
+                                 f"cheap r={cw.radius} vs plain r={fw.radius}",
+        "plain_frames_per_s": 1.0 / t_plain,
+        "plain_gpix_disp_tap_per_s": fw.work_taps / t_plain / 1e9,
+        "net_path_frames_per_s": 1.0 / t_net,
+        "net_bad1_vs_plain": float(np.mean(bad)), "net_mae_vs_plain": float(np.mean(mae)),
+    }
+    for name, frac in (("specified", 0.05), ("calibrated", calib)):
+        if frac is None:
+            continue
+        t = timed(run_gated(frac))
+        rate = float(np.mean([fb[i] for i in range(n)]))
+        b = float(np.mean([0.0 if fb[i] else bad[i] for i in range(n)]))
+        res[f"gate_{name}"] = {"gate_px": 1.0, "gate_frac": frac, "frames_per_s": 1.0 / t,
+                               "fallback_rate": rate, "bad1_vs_plain": b,
+                               "speedup_vs_plain": t_plain / t}
+    sur.close()
+    return res
 
 
 def cpu_baseline(wl, pair, target_s: float):
@@ -158,6 +330,10 @@ def main():
         "mde_per_s": wl.width * wl.height * wl.n_disp * fps / 1e6,
         "roofline": roof,
     }
+    if not args.no_batched:
+        out["batched"] = batched(args, dev)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, pair, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -131,6 +131,118 @@ fbs_status fbs_run(const fbs_params* p, const uint8_t* left, const uint8_t* righ
  * 0 = vector-ALU kernel.  Host only; FBS_E_* on invalid `p`. */
 int fbs_run_variant(const fbs_params* p);
 
+/* ---- Batched plans: many pairs of uneven sizes in one graph launch ---- */
+
+typedef struct fbs_plan fbs_plan;
+
+/* Builds a plan for n pairs (params is a HOST array of n fbs_params; every
+ * pair TAD).  Each pair gets the matrix-core kernel where fbs_run would use
+ * it, with its waves-per-workgroup and disparity-slab depth taken from the
+ * tuning cache at tune_cache_path (JSON, may be NULL), or - when tune is
+ * nonzero and the cache has no entry for the pair's (W, H, C, D, r) - by
+ * timing every candidate on synthetic data of that shape (the cache file is
+ * then rewritten), else from the same heuristic as fbs_run.  Pairs of equal
+ * radius, channels and waves share one persistent kernel that pulls
+ * (pair, tile) items from a work queue; the whole launch sequence is
+ * captured once into a hipGraph.  Allocates device and pinned host memory
+ * and synchronises the device (tuning); not for the hot path.  *out is NULL
+ * on failure.  The per-pixel arithmetic equals fbs_run's, so results are
+ * bit-identical to n separate fbs_run calls. */
+fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
+                           const char* tune_cache_path, int32_t tune);
+
+/* Runs the plan: left, right, disp, disp_sub are HOST arrays of n DEVICE
+ * pointers (images as described by the pair's params; dense int32 / float32
+ * [H][W] maps).  Enqueues a pointer upload, one graph launch and, for pairs
+ * the matrix cores cannot take, one vector-ALU launch each, on `stream`.
+ * Waits (on the host) only for the previous launch's pointer upload. */
+fbs_status fbs_plan_launch(fbs_plan* plan, const uint8_t* const* left,
+                           const uint8_t* const* right, int32_t* const* disp,
+                           float* const* disp_sub, void* stream);
+
+/* Configuration chosen for one pair: matrix_cores (1/0), waves per
+ * workgroup (4 or 8) and disparity-slab depth in blocks of 16 (0 for a
+ * vector-ALU pair).  Any output may be NULL. */
+fbs_status fbs_plan_pair_config(const fbs_plan* plan, int32_t pair, int32_t* matrix_cores,
+                                int32_t* waves, int32_t* slab_blocks);
+
+/* Host-side launches per fbs_plan_launch (1 graph + vector-ALU pairs). */
+int32_t fbs_plan_num_launches(const fbs_plan* plan);
+
+/* Waits for the plan's last launch, then frees it.  NULL is a no-op. */
+void fbs_plan_destroy(fbs_plan* plan);
+
+/* ---- Learned surrogate of the full-radius run ----
+ *
+ * A small convolutional net predicts the subpixel disparity map of a
+ * full-radius run (Section II, all steps) from a cheap small-radius run:
+ *   features  17 BF16 channels per pixel, channel-last [H][W][32] (channels
+ *             17..31 are written as zero): the 8 lowest aggregated costs of
+ *             the cheap run in ascending order (ties to the lower d) divided
+ *             by its cost_cap, their disparity indices (d - d_min)/(D - 1)
+ *             in the same order, and the left intensity / 255.
+ *   net       3x3 zero-padded convolutions 17 -> 32 -> 32 -> 32 -> 1, ReLU
+ *             after the first three; BF16 weights and activations, float32
+ *             sums; the output is added to the cheap run's subpixel map.
+ *   training  mean absolute error against a label map, Adam (beta1 0.9,
+ *             beta2 0.999, eps 1e-8) on float32 master weights.
+ * Parameters are one float32 array of fbs_surrogate_num_params() values:
+ * w0 [3][3][32][17], b0 [32], w1 [3][3][32][32], b1 [32], w2 [3][3][32][32],
+ * b2 [32], w3 [3][3][1][32], b3 [1]; weight [ky][kx][out][in] multiplies the
+ * input at image offset (ky - 1, kx - 1).  Feature, map and gradient
+ * pointers are DEVICE pointers; feat must be 16-byte aligned. */
+typedef struct fbs_surrogate fbs_surrogate;
+
+int32_t fbs_surrogate_num_params(void);
+
+/* Allocates weights (all zero), Adam state and buffers for frames up to
+ * max_width x max_height and, for fbs_surrogate_run, cheap runs of up to
+ * max_disp disparities (8..FBS_MAX_DISP).  Synchronises the device. */
+fbs_status fbs_surrogate_create(fbs_surrogate** out, int32_t max_width, int32_t max_height,
+                                int32_t max_disp);
+
+/* Waits for the device, then frees the object.  NULL is a no-op. */
+void fbs_surrogate_destroy(fbs_surrogate* s);
+
+/* Copies fbs_surrogate_num_params() float32 values from / to HOST memory.
+ * set_params also clears the Adam state.  Both synchronise the device. */
+fbs_status fbs_surrogate_set_params(fbs_surrogate* s, const float* host_params);
+fbs_status fbs_surrogate_get_params(fbs_surrogate* s, float* host_params);
+
+/* Features of a cheap run: `cheap` describes it (gray TAD, D >= 8), agg is
+ * its aggregated volume [D][H][W] (fbs_run's agg_out), feat receives
+ * [H][W][32] BF16 (uint16 bit patterns). */
+fbs_status fbs_surrogate_features(fbs_surrogate* s, const fbs_params* cheap, const uint8_t* left,
+                                  const float* agg, uint16_t* feat, void* stream);
+
+/* Prediction: pred[H][W] = cheap_sub + net(feat). */
+fbs_status fbs_surrogate_forward(fbs_surrogate* s, int32_t width, int32_t height,
+                                 const uint16_t* feat, const float* cheap_sub, float* pred,
+                                 void* stream);
+
+/* Forward plus backward of the mean absolute error against label[H][W]:
+ * pred receives the prediction, grads (num_params float32, device) the
+ * gradient in the packed order, loss (device float, may be NULL) the loss.
+ * Uses the object's buffers: calls on one object must not overlap. */
+fbs_status fbs_surrogate_gradients(fbs_surrogate* s, int32_t width, int32_t height,
+                                   const uint16_t* feat, const float* cheap_sub,
+                                   const float* label, float* pred, float* grads, float* loss,
+                                   void* stream);
+
+/* One Adam step with learning rate lr on the master weights (device grads). */
+fbs_status fbs_surrogate_adam(fbs_surrogate* s, const float* grads, float lr, void* stream);
+
+/* Inference with fallback: runs `cheap` (fbs_run, aggregated volume kept in
+ * the object), the features and the net into disp_sub; counts pixels where
+ * the prediction and the cheap subpixel map differ by more than gate_px, and
+ * when that count exceeds gate_frac * W * H reruns `full` (same pair and
+ * disparity range, e.g. the full radius) into disp_sub and sets *fell_back
+ * to 1 (else 0; fell_back may be NULL).  Synchronises `stream` once, for the
+ * count. */
+fbs_status fbs_surrogate_run(fbs_surrogate* s, const fbs_params* cheap, const fbs_params* full,
+                             const uint8_t* left, const uint8_t* right, float* disp_sub,
+                             float gate_px, float gate_frac, int32_t* fell_back, void* stream);
+
 /* Static description of a status code. */
 const char* fbs_status_str(int status);
 

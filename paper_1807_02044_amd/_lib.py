@@ -34,7 +34,12 @@ FBS_F_FORCE_VALU = 0x1
 # Entry points declared in include/fbs.h (checked by the ABI tests).
 EXPORTS = (
     "fbs_validate", "fbs_workspace_bytes", "fbs_cost", "fbs_aggregate", "fbs_wta_subpixel",
-    "fbs_run", "fbs_run_variant", "fbs_status_str", "fbs_last_error", "fbs_version",
+    "fbs_run", "fbs_run_variant", "fbs_plan_create", "fbs_plan_launch", "fbs_plan_pair_config",
+    "fbs_plan_num_launches", "fbs_plan_destroy", "fbs_surrogate_num_params",
+    "fbs_surrogate_create", "fbs_surrogate_destroy", "fbs_surrogate_set_params",
+    "fbs_surrogate_get_params", "fbs_surrogate_features", "fbs_surrogate_forward",
+    "fbs_surrogate_gradients", "fbs_surrogate_adam", "fbs_surrogate_run", "fbs_status_str",
+    "fbs_last_error", "fbs_version",
 )
 
 
@@ -91,6 +96,41 @@ def lib() -> ctypes.CDLL:
         h.fbs_run_variant.argtypes = [P]
         for f in (h.fbs_validate, h.fbs_workspace_bytes, h.fbs_cost, h.fbs_aggregate,
                   h.fbs_wta_subpixel, h.fbs_run, h.fbs_run_variant):
+            f.restype = ctypes.c_int
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        h.fbs_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, P,
+                                      ctypes.c_char_p, ctypes.c_int32]
+        h.fbs_plan_create.restype = ctypes.c_int
+        h.fbs_plan_launch.argtypes = [vp, pp, pp, pp, pp, vp]
+        h.fbs_plan_launch.restype = ctypes.c_int
+        h.fbs_plan_pair_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32)]
+        h.fbs_plan_pair_config.restype = ctypes.c_int
+        h.fbs_plan_num_launches.argtypes = [vp]
+        h.fbs_plan_num_launches.restype = ctypes.c_int32
+        h.fbs_plan_destroy.argtypes = [vp]
+        h.fbs_plan_destroy.restype = None
+        fp = ctypes.POINTER(ctypes.c_float)
+        h.fbs_surrogate_num_params.argtypes = []
+        h.fbs_surrogate_num_params.restype = ctypes.c_int32
+        h.fbs_surrogate_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_int32]
+        h.fbs_surrogate_destroy.argtypes = [vp]
+        h.fbs_surrogate_destroy.restype = None
+        h.fbs_surrogate_set_params.argtypes = [vp, fp]
+        h.fbs_surrogate_get_params.argtypes = [vp, fp]
+        h.fbs_surrogate_features.argtypes = [vp, P, vp, vp, vp, vp]
+        h.fbs_surrogate_forward.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
+        h.fbs_surrogate_gradients.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
+                                              vp, vp, vp, vp]
+        h.fbs_surrogate_adam.argtypes = [vp, vp, ctypes.c_float, vp]
+        h.fbs_surrogate_run.argtypes = [vp, P, P, vp, vp, vp, ctypes.c_float, ctypes.c_float,
+                                        ctypes.POINTER(ctypes.c_int32), vp]
+        for f in (h.fbs_surrogate_create, h.fbs_surrogate_set_params,
+                  h.fbs_surrogate_get_params, h.fbs_surrogate_features,
+                  h.fbs_surrogate_forward, h.fbs_surrogate_gradients, h.fbs_surrogate_adam,
+                  h.fbs_surrogate_run):
             f.restype = ctypes.c_int
         h.fbs_status_str.argtypes = [ctypes.c_int]
         h.fbs_status_str.restype = ctypes.c_char_p
@@ -175,3 +215,108 @@ def fbs_last_error() -> str:
 
 def fbs_version() -> str:
     return lib().fbs_version().decode()
+
+
+class FbsPlan:
+    """Batched plan (fbs_plan_create / fbs_plan_launch / fbs_plan_destroy)."""
+
+    def __init__(self, params, tune_cache: Optional[str] = None, tune: bool = False):
+        arr = (FbsParams * len(params))(*params)
+        h = ctypes.c_void_p(None)
+        path = tune_cache.encode() if tune_cache else None
+        _check(lib().fbs_plan_create(ctypes.byref(h), len(params), arr, path, int(bool(tune))))
+        self.handle = h
+        self.n = len(params)
+
+    def launch(self, lefts, rights, disps, subs, stream=None):
+        n = self.n
+        if not (len(lefts) == len(rights) == len(disps) == len(subs) == n):
+            raise FbsError(FBS_E_INVALID, f"need {n} buffers of each kind")
+
+        def arr(ts):
+            return (ctypes.c_void_p * n)(*[_ptr(t) for t in ts])
+
+        _check(lib().fbs_plan_launch(self.handle, arr(lefts), arr(rights), arr(disps), arr(subs),
+                                     _stream(stream)))
+
+    def pair_config(self, i: int):
+        m, w, b = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().fbs_plan_pair_config(self.handle, i, ctypes.byref(m), ctypes.byref(w),
+                                          ctypes.byref(b)))
+        return int(m.value), int(w.value), int(b.value)
+
+    def num_launches(self) -> int:
+        return int(lib().fbs_plan_num_launches(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib().fbs_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FbsSurrogate:
+    """Learned surrogate object (fbs_surrogate_*).  Parameters are numpy
+    float32 arrays in the packed order; buffers are device tensors."""
+
+    def __init__(self, max_width: int, max_height: int, max_disp: int):
+        h = ctypes.c_void_p(None)
+        _check(lib().fbs_surrogate_create(ctypes.byref(h), max_width, max_height, max_disp))
+        self.handle = h
+        self.n_params = int(lib().fbs_surrogate_num_params())
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != self.n_params:
+            raise FbsError(FBS_E_INVALID, f"need {self.n_params} parameters, got {a.size}")
+        _check(lib().fbs_surrogate_set_params(
+            self.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().fbs_surrogate_get_params(
+            self.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return a
+
+    def features(self, cheap: FbsParams, left, agg, feat, stream=None):
+        _check(lib().fbs_surrogate_features(self.handle, ctypes.byref(cheap), _ptr(left),
+                                            _ptr(agg), _ptr(feat), _stream(stream)))
+
+    def forward(self, width: int, height: int, feat, cheap_sub, pred, stream=None):
+        _check(lib().fbs_surrogate_forward(self.handle, width, height, _ptr(feat),
+                                           _ptr(cheap_sub), _ptr(pred), _stream(stream)))
+
+    def gradients(self, width: int, height: int, feat, cheap_sub, label, pred, grads,
+                  loss=None, stream=None):
+        _check(lib().fbs_surrogate_gradients(self.handle, width, height, _ptr(feat),
+                                             _ptr(cheap_sub), _ptr(label), _ptr(pred),
+                                             _ptr(grads), _ptr(loss), _stream(stream)))
+
+    def adam(self, grads, lr: float, stream=None):
+        _check(lib().fbs_surrogate_adam(self.handle, _ptr(grads), float(lr), _stream(stream)))
+
+    def run(self, cheap: FbsParams, full: FbsParams, left, right, disp_sub, gate_px: float,
+            gate_frac: float, stream=None) -> bool:
+        fb = ctypes.c_int32(0)
+        _check(lib().fbs_surrogate_run(self.handle, ctypes.byref(cheap), ctypes.byref(full),
+                                       _ptr(left), _ptr(right), _ptr(disp_sub), float(gate_px),
+                                       float(gate_frac), ctypes.byref(fb), _stream(stream)))
+        return bool(fb.value)
+
+    def close(self):
+        if self.handle:
+            lib().fbs_surrogate_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

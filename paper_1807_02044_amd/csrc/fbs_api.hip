@@ -108,6 +108,23 @@ bool aligned4(const void* q) { return ((uintptr_t)q & 3u) == 0; }
 
 }  // namespace
 
+namespace fbs {
+// Shared with the plan layer (fbs_plan.hip).
+fbs_status api_check_params(const fbs_params* p) { return check_params(p); }
+Geom api_geom(const fbs_params* p) { return make_geom(p); }
+Tables api_tables(const fbs_params* p) { return make_tables(p); }
+fbs_status api_fail(fbs_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+}  // namespace fbs
+
 extern "C" {
 
 fbs_status fbs_validate(const fbs_params* p) { return check_params(p); }

@@ -52,8 +52,46 @@ hipError_t launch_valu(const Geom& g, const Tables& t, CostSrc src, const uint8_
                        int32_t* disp, float* sub, hipStream_t s);
 
 // Fused TAD path on the matrix cores.
+struct MfmaCfg {
+    int nw;  // waves per workgroup: 4 (8x8 pixel tiles) or 8 (8x16)
+    int nb;  // 16-disparity blocks per LDS slab
+};
 bool mfma_supported(const Geom& g);
+float mfma_scaled_cap(const Geom& g);
+int mfma_max_nb(const Geom& g, int nw);
+int mfma_lds_bytes(const Geom& g, int nb, int nw);
 hipError_t launch_mfma(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
                        int32_t* disp, float* sub, float* agg, hipStream_t s);
+hipError_t launch_mfma_cfg(const Geom& g, const Tables& t, const MfmaCfg& cfg, const uint8_t* L,
+                           const uint8_t* R, int32_t* disp, float* sub, float* agg, hipStream_t s);
+
+// One pair of a batch, as the persistent kernel reads it from device memory.
+struct BatchPair {
+    Geom g;
+    float scap;
+    int nb;
+    int tiles_x;
+    int pad;
+    Tables tb;
+};
+
+// One persistent launch: every (pair, tile) item of one (radius, channels,
+// waves) class; items[i] = (pair index, tile index), pointer arrays indexed
+// by pair.
+struct BatchClass {
+    int r, ch, nw;
+    int lds;  // dynamic LDS bytes: the largest layout of any pair in the class
+    int grid;
+    const BatchPair* pairs;
+    const int2* items;
+    int n_items;
+    int* counter;
+    const uint8_t* const* L;
+    const uint8_t* const* R;
+    int32_t* const* disp;
+    float* const* sub;
+};
+hipError_t launch_mfma_batch(const BatchClass& bc, hipStream_t s);
+int mfma_batch_blocks_per_cu(int r, int ch, int nw, int lds_bytes);
 
 }  // namespace fbs

@@ -38,16 +38,14 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 8;
-constexpr int kThreads = kWaves * 64;
-constexpr int kTileH = 8, kTileW = 16;
+constexpr int kTileH = 8;         // tile rows; a tile is kTileH x (2 * waves) pixels
 constexpr float kWScale = 16384.0f;  // 2^14: keeps small weights in fp16's normal range
 constexpr int kMaxR = 10;
 
 constexpr int n_chunks(int gh, int gw, int r) { return (((gh + 2 * r) * ((gw + 2 * r + 7) / 8)) + 3) / 4; }
 
 // Geometry of one radius: group shape (the one with fewer K chunks), octets,
-// chunks, and the LDS tile of the 8x16 workgroup tile.
+// chunks, and the LDS tile of a kTileH x tile_w workgroup tile.
 struct Cfg {
     int GH, GW;  // group shape
     int OPR;     // 8-wide octets per union row
@@ -60,7 +58,7 @@ struct Cfg {
     int PS;
 };
 
-__host__ __device__ constexpr Cfg cfg_of(int r)
+__host__ __device__ constexpr Cfg cfg_of(int r, int tile_w)
 {
     const bool wide = n_chunks(2, 8, r) <= n_chunks(4, 4, r);
     Cfg c{};
@@ -69,7 +67,7 @@ __host__ __device__ constexpr Cfg cfg_of(int r)
     c.OPR = (c.GW + 2 * r + 7) / 8;
     c.NOCT = (c.GH + 2 * r) * c.OPR;
     c.NCH = (c.NOCT + 3) / 4;
-    c.GX = kTileW / c.GW;
+    c.GX = tile_w / c.GW;
     c.GY = kTileH / c.GH;
     c.LH = kTileH + 2 * r;
     c.LW = ((c.GX - 1) * c.GW + 8 * c.OPR + 7) / 8 * 8;
@@ -80,19 +78,24 @@ __host__ __device__ constexpr Cfg cfg_of(int r)
 __host__ __device__ constexpr int align16(int b) { return (b + 15) & ~15; }
 
 struct MfmaLayout {
-    int rw;           // bytes per right-strip row
-    int off_L, off_R, off_cost;
+    int lwb, rwb;     // bytes per left-tile / right-strip row (channels interleaved)
+    int off_wx, off_wy, off_L, off_R, off_cost;
     int bytes;
 };
 
-__host__ __device__ constexpr MfmaLayout mfma_layout(int r, int ch, int D, int nb)
+__host__ __device__ constexpr MfmaLayout mfma_layout(int r, int ch, int D, int nb, int nw)
 {
-    const Cfg c = cfg_of(r);
+    const int tile_w = 2 * nw;
+    const Cfg c = cfg_of(r, tile_w);
     MfmaLayout m{};
-    m.rw = (c.LW + D - 1 + 4 + 3) & ~3;  // +4: the last unaligned 8-byte read
-    m.off_L = (256 + 32) * 4;
-    m.off_R = m.off_L + align16(ch * c.LH * c.LW);
-    m.off_cost = m.off_R + align16(ch * c.LH * m.rw);
+    m.lwb = ch * c.LW;
+    // +16: slack for the unaligned reads of the last octet of a row
+    m.rwb = (ch * (c.LW + D - 1) + 16 + 3) & ~3;
+    m.off_wx = (256 + 32) * 4;  // after the range LUT and the spatial factors
+    m.off_wy = m.off_wx + tile_w * c.LW * 4;
+    m.off_L = m.off_wy + align16(kTileH * c.LH * 4);
+    m.off_R = m.off_L + align16(c.LH * m.lwb);
+    m.off_cost = m.off_R + align16(c.LH * m.rwb);
     m.bytes = m.off_cost + 16 * nb * c.PS * 2;
     return m;
 }
@@ -107,109 +110,143 @@ __device__ __forceinline__ h8 lds_h8(const _Float16* p)
 }
 
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
-// Bytes b0,b1 of v as the fp16 pair (1024 + b0, 1024 + b1): the byte fills the
-// mantissa under the exponent of 1024 (0x6400), so differences are exact.
+// v_perm_b32 picks bytes of the 64-bit {hi, lo} (selector 0-3: lo, 4-7: hi,
+// 0x0c: zero).  With hi = 0x64646464, bytes b0, b1 of lo become the fp16 pair
+// (1024 + b0, 1024 + b1): the byte fills the mantissa under the exponent of
+// 1024, so differences of such pairs are exact.
 __device__ __forceinline__ h2 bytes01_f16(uint32_t v)
 {
-    return __builtin_bit_cast(h2, (v & 0xffu) | ((v & 0xff00u) << 8) | 0x64006400u);
+    return __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, v, 0x04010400u));
 }
 __device__ __forceinline__ h2 bytes23_f16(uint32_t v)
 {
-    return __builtin_bit_cast(h2, ((v >> 16) & 0xffu) | ((v >> 8) & 0xff0000u) | 0x64006400u);
+    return __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, v, 0x04030402u));
 }
 
-// 8 right-image bytes starting at an arbitrary byte offset (3 aligned dword
-// reads; the row padding of the strip keeps the third read in bounds).
-__device__ __forceinline__ void load8_unaligned(const uint8_t* p, uint32_t& lo, uint32_t& hi)
+// Dwords w[0..N-1] of an LDS byte array starting at an arbitrary byte offset:
+// N+1 aligned dword reads (the row slack of the strip keeps the last in bounds).
+template <int N>
+__device__ __forceinline__ void load_unaligned(const uint8_t* base, int off, uint32_t (&w)[N])
 {
-    const uintptr_t a = (uintptr_t)p;
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(a & ~(uintptr_t)3);
-    const uint32_t sh = (uint32_t)(a & 3);
-    const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-    lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
-    hi = __builtin_amdgcn_alignbyte(w2, w1, sh);
+    const uint32_t* a = reinterpret_cast<const uint32_t*>(base) + (off >> 2);
+    const uint32_t sh = (uint32_t)(off & 3);
+    uint32_t t[N + 1];
+#pragma unroll
+    for (int i = 0; i <= N; ++i) t[i] = a[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] = __builtin_amdgcn_alignbyte(t[i + 1], t[i], sh);
 }
 
-// TAD cost (times the channel count) of 8 interior positions in packed fp16:
-// min(sum_ch |L - R|, scap), exact because every term is an integer <= 765.
-template <int CH>
-__device__ __forceinline__ h8 octet_cost(const uint8_t* l, const uint8_t* r, int lplane,
-                                         int rplane, float scap)
+// Pixel j (bytes 3j..3j+2, zero-extended) of 8 interleaved RGB pixels.
+__device__ __forceinline__ uint32_t rgb_pixel(const uint32_t (&a)[6], int j)
 {
-    h2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-#pragma unroll
-    for (int ch = 0; ch < CH; ++ch) {
-        const uint2 lv = *reinterpret_cast<const uint2*>(l + ch * lplane);
-        uint32_t r0, r1;
-        load8_unaligned(r + ch * rplane, r0, r1);
-        const h2 lp[4] = {bytes01_f16(lv.x), bytes23_f16(lv.x), bytes01_f16(lv.y), bytes23_f16(lv.y)};
-        const h2 rp[4] = {bytes01_f16(r0), bytes23_f16(r0), bytes01_f16(r1), bytes23_f16(r1)};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] += __builtin_elementwise_abs(lp[i] - rp[i]);
-    }
-    const _Float16 ch = (_Float16)scap;
-    const h2 cap = {ch, ch};
-    h8 out;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const h2 c = __builtin_elementwise_min(acc[i], cap);
-        out[2 * i] = c[0];
-        out[2 * i + 1] = c[1];
-    }
-    return out;
+    const int b = 3 * j, i = b >> 2, s = b & 3;
+    const uint32_t hi = a[i + 1 < 6 ? i + 1 : 5];
+    return __builtin_amdgcn_perm(hi, a[i], 0x0c000000u | ((s + 2) << 16) | ((s + 1) << 8) | s);
 }
 
-template <int R, int CH>
-__global__ __launch_bounds__(kThreads) void k_fbs_mfma(Geom g, Tables tb, int nb, float scap,
-                                                       const uint8_t* __restrict__ Lg,
-                                                       const uint8_t* __restrict__ Rg,
-                                                       int32_t* __restrict__ disp,
-                                                       float* __restrict__ sub,
-                                                       float* __restrict__ agg)
+// fp16 pair (s0, s1) of two integers below 1024
+__device__ __forceinline__ h2 small_int_pair(uint32_t s0, uint32_t s1)
 {
-    constexpr Cfg C = cfg_of(R);
+    const h2 off = {(_Float16)1024.0f, (_Float16)1024.0f};
+    return __builtin_bit_cast(h2, (s0 | (s1 << 16)) | 0x64006400u) - off;
+}
+
+// One tile's worth of work, shared by the per-frame and the batched kernels.
+struct TileJob {
+    Geom g;
+    float scap;  // cap as the kernel sees it (tau, or 3 tau for RGB)
+    int nb;      // 16-disparity blocks per LDS slab
+    const uint8_t* L;
+    const uint8_t* R;
+    int32_t* disp;
+    float* sub;
+    float* agg;
+};
+
+// The caller has put the range LUT (256 floats) at smem[0] and the spatial
+// factors exp(-k^2/gd^2), k = 0..31 (0 beyond the radius), right after it,
+// and synchronised the workgroup.
+template <int R, int CH, int NW>
+__device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int tile_y,
+                                          unsigned char* smem)
+{
+    constexpr int kThreads = 64 * NW, kTileW = 2 * NW;
+    const Geom& g = job.g;
+    const int nb = job.nb;
+    const float scap = job.scap;
+    const uint8_t* __restrict__ Lg = job.L;
+    const uint8_t* __restrict__ Rg = job.R;
+    int32_t* __restrict__ disp = job.disp;
+    float* __restrict__ sub = job.sub;
+    float* __restrict__ agg = job.agg;
+    constexpr Cfg C = cfg_of(R, kTileW);
     constexpr int GH = C.GH, GW = C.GW, OPR = C.OPR, NOCT = C.NOCT, NCH = C.NCH;
     constexpr int LH = C.LH, LW = C.LW, PS = C.PS;
-    static_assert(C.GX * C.GY == kWaves, "one group per wave");
-    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int LWB = CH * LW;
+    static_assert(C.GX * C.GY == NW, "one group per wave");
 
     const int D = g.D;
     const int nblk = (D + 15) >> 4;   // 16-disparity blocks
     const int Q = nblk * 4;           // disparities per lane group
-    const MfmaLayout lay = mfma_layout(R, CH, D, nb);
-    const int RW = lay.rw;
-    float* s_gr = reinterpret_cast<float*>(smem);
-    float* s_gs = s_gr + 256;
+    const MfmaLayout lay = mfma_layout(R, CH, D, nb, NW);
+    const int RWB = lay.rwb;
+    const float* s_gr = reinterpret_cast<const float*>(smem);
+    const float* s_gs = s_gr + 256;
+    float* s_wx = reinterpret_cast<float*>(smem + lay.off_wx);
+    float* s_wy = reinterpret_cast<float*>(smem + lay.off_wy);
     uint8_t* s_L = smem + lay.off_L;
     uint8_t* s_R = smem + lay.off_R;
     _Float16* s_cost = reinterpret_cast<_Float16*>(smem + lay.off_cost);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int X0 = blockIdx.x * kTileW, Y0 = blockIdx.y * kTileH;
+    const int X0 = tile_x * kTileW, Y0 = tile_y * kTileH;
     const int ox = X0 - R, oy = Y0 - R;           // image position of LDS tile (0,0)
     const int dmax = g.dmin + D - 1;
     const int rox = ox - dmax;                    // image x of right-strip column 0
 
-    // ---- stage lookup tables, left tile and right strip (0 off-image) ----
-    for (int i = tid; i < 256; i += kThreads) s_gr[i] = tb.gr[i];
-    if (tid < 32) s_gs[tid] = (tid <= R) ? tb.gs[tid] : 0.0f;
-    for (int i = tid; i < CH * LH * LW; i += kThreads) {
-        const int ch = i / (LH * LW), rem = i - ch * (LH * LW);
-        const int row = rem / LW, col = rem - row * LW;
-        const int x = ox + col, y = oy + row;
-        uint8_t v = 0;
-        if (x >= 0 && x < g.W && y >= 0 && y < g.H) v = Lg[(size_t)y * g.stride + (size_t)x * CH + ch];
-        s_L[i] = v;
+    // ---- stage: range LUT; spatial factor tables; left tile, right strip ----
+    // s_wx[pc][U] = exp(-(U-R-pc)^2/gd^2) for union column U of pixel column pc,
+    // 0 outside the window or the image; s_wy[pr][V] likewise along y, times
+    // the 2^14 weight scale.  Image rows are copied as bytes with channels
+    // interleaved; bytes off the image are staged as 0.
+    for (int i = tid; i < kTileW * LW; i += kThreads) {
+        const int pc = i / LW, u = i - pc * LW;
+        const int dx = abs(u - R - pc), x = ox + u;
+        s_wx[i] = (dx <= R && x >= 0 && x < g.W) ? s_gs[dx] : 0.0f;
     }
-    for (int i = tid; i < CH * LH * RW; i += kThreads) {
-        const int ch = i / (LH * RW), rem = i - ch * (LH * RW);
-        const int row = rem / RW, col = rem - row * RW;
-        const int x = rox + col, y = oy + row;
-        uint8_t v = 0;
-        if (x >= 0 && x < g.W && y >= 0 && y < g.H) v = Rg[(size_t)y * g.stride + (size_t)x * CH + ch];
-        s_R[i] = v;
+    for (int i = tid; i < kTileH * LH; i += kThreads) {
+        const int pr = i / LH, v = i - pr * LH;
+        const int dy = abs(v - R - pr), y = oy + v;
+        s_wy[i] = (dy <= R && y >= 0 && y < g.H) ? s_gs[dy] * kWScale : 0.0f;
+    }
+    {
+        // Bytes off the image are never weighted (their window positions have
+        // zero weight, and right pixels left of the image are replaced by the
+        // cap), so they only need to be finite: read them from clamped
+        // in-bounds addresses instead of branching.  4 bytes per thread and
+        // iteration, all loads issued before the LDS writes.
+        const int rowbytes = g.W * CH;
+        auto stage = [&](uint8_t* dst, int wb, int xb0, const uint8_t* src) {
+            const int n4 = LH * wb / 4;
+#pragma unroll 2
+            for (int i = tid; i < n4; i += kThreads) {
+                const int row = (4 * i) / wb, cb = 4 * i - row * wb;
+                const size_t rbase = (size_t)min(max(oy + row, 0), g.H - 1) * g.stride;
+                uint32_t v = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int xb = min(max(xb0 + cb + e, 0), rowbytes - 1);
+                    v |= (uint32_t)src[rbase + xb] << (8 * e);
+                }
+                reinterpret_cast<uint32_t*>(dst)[i] = v;
+            }
+        };
+        stage(s_L, LWB, ox * CH, Lg);
+        stage(s_R, RWB, rox * CH, Rg);
     }
     __syncthreads();
 
@@ -221,53 +258,60 @@ __global__ __launch_bounds__(kThreads) void k_fbs_mfma(Geom g, Tables tb, int nb
     const bool pin = px < g.W && py < g.H;
 
     // ---- support weights (Eqs. 7-8) for this lane's pixel, hi/lo fp16 ----
+    // w = wx(dx) * wy(dy) * prod_ch gr(|dI_ch|) * 2^14, then w = hi + lo
     uint32_t lp[CH];
 #pragma unroll
-    for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(ch * LH + prow + R) * LW + pcol + R];
+    for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(prow + R) * LWB + (pcol + R) * CH + ch];
     h8 whi[NCH], wlo[NCH];
-    float den = 0.0f;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-        const int o = 4 * c + gq;
-        const bool real = o < NOCT;
-        const int urow = real ? o / OPR : 0;
-        const int ucol0 = real ? (o % OPR) * 8 : 0;
-        const int dy = urow - R - n / GW;
-        const float wdy = s_gs[min(abs(dy), 31)];
-        const int qy = oy + grow0 + urow;
-        const bool rowok = real && qy >= 0 && qy < g.H;
-        const uint8_t* lrow = s_L + (grow0 + urow) * LW + gcol0 + ucol0;
-        uint32_t hb[4], lb[4];
+        const int o = min(4 * c + gq, NOCT - 1);  // octets past the union: weight 0
+        const bool real = 4 * c + gq < NOCT;
+        const int V = grow0 + o / OPR;                          // tile union row
+        const int U = gcol0 + (o % OPR) * 8;                    // tile union column
+        const float wy = real ? s_wy[prow * LH + V] : 0.0f;
+        const float4 wx0 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U);
+        const float4 wx1 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U + 4);
+        const float wx[8] = {wx0.x, wx0.y, wx0.z, wx0.w, wx1.x, wx1.y, wx1.z, wx1.w};
+        // 8 pixels x CH channels of the left image, as dwords (U*CH is a multiple of 4)
+        uint32_t lq[2 * CH];
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(s_L + V * LWB + U * CH);
+#pragma unroll
+        for (int i = 0; i < 2 * CH; ++i) lq[i] = q[i];
+        float w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float wr = 1.0f;
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch) {
+                const int b = CH * j + ch;
+                const int iv = (int)((lq[b >> 2] >> (8 * (b & 3))) & 0xffu);
+                const float f = s_gr[abs(iv - (int)lp[ch])];
+                wr = ch == 0 ? f : wr * f;
+            }
+            w[j] = (wx[j] * wy) * wr;
+        }
+        h8 hv, lv;
 #pragma unroll
         for (int j2 = 0; j2 < 4; ++j2) {
-            uint32_t hh = 0, ll = 0;
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int j = 2 * j2 + e;
-                const int ucol = ucol0 + j;
-                const int dx = ucol - R - n % GW;
-                const int qx = ox + gcol0 + ucol;
-                float w = 0.0f;
-                if (rowok && ucol < GW + 2 * R && qx >= 0 && qx < g.W) {
-                    float wr = s_gr[abs((int)lrow[j] - (int)lp[0])];
-                    if (CH == 3) {
-                        wr *= s_gr[abs((int)lrow[LH * LW + j] - (int)lp[1])];
-                        wr *= s_gr[abs((int)lrow[2 * LH * LW + j] - (int)lp[2])];
-                    }
-                    w = ((wdy * s_gs[min(abs(dx), 31)]) * wr) * kWScale;
-                }
-                const _Float16 hi = (_Float16)w;
-                const _Float16 lo = (_Float16)(w - (float)hi);
-                hh |= (uint32_t)__builtin_bit_cast(uint16_t, hi) << (16 * e);
-                ll |= (uint32_t)__builtin_bit_cast(uint16_t, lo) << (16 * e);
-            }
-            hb[j2] = hh;
-            lb[j2] = ll;
+            const f2 pw = {w[2 * j2], w[2 * j2 + 1]};
+            const h2 hi = __builtin_convertvector(pw, h2);
+            const h2 lo = __builtin_convertvector(pw - __builtin_convertvector(hi, f2), h2);
+            hv[2 * j2] = hi[0];
+            hv[2 * j2 + 1] = hi[1];
+            lv[2 * j2] = lo[0];
+            lv[2 * j2 + 1] = lo[1];
         }
-        whi[c] = __builtin_bit_cast(h8, make_uint4(hb[0], hb[1], hb[2], hb[3]));
-        wlo[c] = __builtin_bit_cast(h8, make_uint4(lb[0], lb[1], lb[2], lb[3]));
-        __builtin_amdgcn_sched_barrier(0);  // keep one chunk's temporaries live at a time
+        // Pin the packed chunk here.  Otherwise the conversions sink towards their
+        // MFMA uses and all float weights of the tile stay live at once.
+        uint4 hu = __builtin_bit_cast(uint4, hv), lu = __builtin_bit_cast(uint4, lv);
+        asm volatile("" : "+v"(hu.x), "+v"(hu.y), "+v"(hu.z), "+v"(hu.w), "+v"(lu.x), "+v"(lu.y),
+                     "+v"(lu.z), "+v"(lu.w));
+        whi[c] = __builtin_bit_cast(h8, hu);
+        wlo[c] = __builtin_bit_cast(h8, lu);
     }
+    float den = 0.0f;
+    const float inv_scale = 1.0f / (CH == 3 ? 3.0f : 1.0f);
     if (agg) {
         // Eq. 6's denominator: an all-ones A operand sums each weight column,
         // giving sum_q (hi + lo)(p, q) for pixel p in every lane of that pixel
@@ -282,7 +326,6 @@ __global__ __launch_bounds__(kThreads) void k_fbs_mfma(Geom g, Tables tb, int nb
         }
         den = dh[0] + dl[0];
     }
-    const float inv_scale = 1.0f / (CH == 3 ? 3.0f : 1.0f);
 
     // ---- running WTA over this lane's quarter of the disparity range ----
     const float kInf = __builtin_inff();
@@ -303,72 +346,115 @@ __global__ __launch_bounds__(kThreads) void k_fbs_mfma(Geom g, Tables tb, int nb
         const int o = 4 * c + gq;
         a_base[c] = (o / OPR) * LW + (o % OPR) * 8;
     }
-    auto a_off = [&](int c) {
-        const int o = 4 * c + gq;
-        // octets past the union (zero weight) read a valid in-plane offset
-        const int real_off = a_base[c % P] + (c / P) * kRowsPerPeriod * LW;
-        return (4 * c + 3 < NOCT || o < NOCT) ? real_off : 0;
+    auto a_off = [&](int c) -> int {
+        if (4 * c + 3 < NOCT) return a_base[c % P] + (c / P) * kRowsPerPeriod * LW;
+        // last chunk: octets past the union carry zero weight; read the last real one
+        const int o = min(4 * c + gq, NOCT - 1);
+        return (o / OPR) * LW + (o % OPR) * 8;
     };
     const int nslab = (nblk + nb - 1) / nb;
     constexpr int kOct = LW / 8;
+    const _Float16 hcap = (_Float16)scap;
+    const h2 cap2 = {hcap, hcap};
     for (int s = 0; s < nslab; ++s) {
         const int b0 = s * nb;
         const int nbb = min(nb, nblk - b0);
         __syncthreads();  // every wave is done with the previous slab
-        // cost planes: plane p = 16*bb + m, m = 4*gm + jm <-> disparity index
-        // k = gm*Q + 4*(b0+bb) + jm; each item writes 8 consecutive positions
-        const int items = nbb * 16 * LH * kOct;
+        // Cost planes: plane p = 16*bb + 4*gm + jm holds disparity index
+        // k = gm*Q + 4*(b0+bb) + jm.  An item is one octet (8 positions of a
+        // tile row) at the 4 consecutive disparities jm = 0..3 of one (bb, gm).
+        // Costs of positions off the image or of padded disparities are never
+        // weighted, so any finite value will do there.
+        const int items = 4 * nbb * LH * kOct;
 #pragma unroll 1
         for (int it = tid; it < items; it += kThreads) {
             const int oc = it % kOct;
             const int t = it / kOct;
             const int row = t % LH;
-            const int p = t / LH;
-            const int m = p & 15;
-            const int k = (m >> 2) * Q + 4 * (b0 + (p >> 4)) + (m & 3);
-            const int d = g.dmin + min(k, D - 1);      // padded planes read in-bounds
-            const int y = oy + row;
+            const int quad = t / LH;                      // 4*bb + gm
+            const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
             const int x0 = ox + 8 * oc;
-            const bool rowin = k < D && y >= 0 && y < g.H;
-            const int lb = row * LW + 8 * oc;            // left bytes of this octet
-            const int rb = row * RW + 8 * oc + (dmax - d);  // right bytes it is matched to
-            h8 out;
-            if (rowin && x0 >= 0 && x0 + 7 < g.W && x0 - d >= 0) {
-                out = octet_cost<CH>(s_L + lb, s_R + rb, LH * LW, LH * RW, scap);
+            _Float16* dst = s_cost + (size_t)(4 * quad) * PS + row * LW + 8 * oc;
+            if (CH == 1) {
+                const uint2 lv = *reinterpret_cast<const uint2*>(s_L + row * LWB + 8 * oc);
+                const h2 l0 = bytes01_f16(lv.x), l1 = bytes23_f16(lv.x);
+                const h2 l2 = bytes01_f16(lv.y), l3 = bytes23_f16(lv.y);
+#pragma unroll
+                for (int jm = 0; jm < 4; ++jm) {
+                    const int d = g.dmin + min(k0 + jm, D - 1);
+                    uint32_t r[2];
+                    load_unaligned<2>(s_R, row * RWB + 8 * oc + (dmax - d), r);
+                    const h2 c0 = __builtin_elementwise_min(__builtin_elementwise_abs(l0 - bytes01_f16(r[0])), cap2);
+                    const h2 c1 = __builtin_elementwise_min(__builtin_elementwise_abs(l1 - bytes23_f16(r[0])), cap2);
+                    const h2 c2 = __builtin_elementwise_min(__builtin_elementwise_abs(l2 - bytes01_f16(r[1])), cap2);
+                    const h2 c3 = __builtin_elementwise_min(__builtin_elementwise_abs(l3 - bytes23_f16(r[1])), cap2);
+                    h8 out = {c0[0], c0[1], c1[0], c1[1], c2[0], c2[1], c3[0], c3[1]};
+                    const int thr = d - x0;                       // positions j < thr: x - d < 0
+                    if (thr > 0) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            if (j < thr) out[j] = hcap;
+                    }
+                    *reinterpret_cast<h8*>(dst + jm * PS) = out;
+                }
             } else {
+                const uint2* lq = reinterpret_cast<const uint2*>(s_L + row * LWB + 24 * oc);
+                const uint2 a0 = lq[0], a1 = lq[1], a2 = lq[2];
+                const uint32_t la[6] = {a0.x, a0.y, a1.x, a1.y, a2.x, a2.y};
+                uint32_t lpx[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int x = x0 + j;
-                    int sad = 0;
+                for (int j = 0; j < 8; ++j) lpx[j] = rgb_pixel(la, j);
 #pragma unroll
-                    for (int ch = 0; ch < CH; ++ch)
-                        sad += abs((int)s_L[ch * LH * LW + lb + j] - (int)s_R[ch * LH * RW + rb + j]);
-                    float c = x - d < 0 ? scap : fminf((float)sad, scap);
-                    c = (rowin && x >= 0 && x < g.W) ? c : 0.0f;
-                    out[j] = (_Float16)c;
+                for (int jm = 0; jm < 4; ++jm) {
+                    const int d = g.dmin + min(k0 + jm, D - 1);
+                    uint32_t ra[6];
+                    load_unaligned<6>(s_R, row * RWB + 24 * oc + 3 * (dmax - d), ra);
+                    uint32_t sad[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) sad[j] = __builtin_amdgcn_sad_u8(lpx[j], rgb_pixel(ra, j), 0u);
+                    h8 out;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const h2 c = __builtin_elementwise_min(small_int_pair(sad[2 * i], sad[2 * i + 1]), cap2);
+                        out[2 * i] = c[0];
+                        out[2 * i + 1] = c[1];
+                    }
+                    const int thr = d - x0;
+                    if (thr > 0) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            if (j < thr) out[j] = hcap;
+                    }
+                    *reinterpret_cast<h8*>(dst + jm * PS) = out;
                 }
             }
-            *reinterpret_cast<h8*>(s_cost + (size_t)p * PS + row * LW + 8 * oc) = out;
         }
         __syncthreads();
 
 #pragma unroll 1
         for (int bb = 0; bb < nbb; ++bb) {
-            f4 acc_h = {0.f, 0.f, 0.f, 0.f};
-            f4 acc_l = {0.f, 0.f, 0.f, 0.f};
+            // two accumulator chains per half (even / odd chunks) so that
+            // consecutive MFMAs are independent; A loads run two chunks ahead
+            f4 acc_h0 = {0.f, 0.f, 0.f, 0.f}, acc_h1 = acc_h0, acc_l0 = acc_h0, acc_l1 = acc_h0;
             const _Float16* plane = s_cost + (size_t)(16 * bb + n) * PS + grow0 * LW + gcol0;
-            // A operand of chunk c: this lane's disparity plane, octet 4c + gq;
-            // loads run one chunk ahead of the MFMAs that consume them
-            h8 a_cur = lds_h8<GW == 8>(plane + a_off(0));
+            h8 a0 = lds_h8<GW == 8>(plane + a_off(0));
+            h8 a1 = NCH > 1 ? lds_h8<GW == 8>(plane + a_off(NCH > 1 ? 1 : 0)) : a0;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                h8 a_nxt = a_cur;
-                if (c + 1 < NCH) a_nxt = lds_h8<GW == 8>(plane + a_off(c + 1));
-                acc_h = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_cur, whi[c], acc_h, 0, 0, 0);
-                acc_l = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_cur, wlo[c], acc_l, 0, 0, 0);
+                h8 a2 = a1;
+                if (c + 2 < NCH) a2 = lds_h8<GW == 8>(plane + a_off(c + 2 < NCH ? c + 2 : 0));
+                if (c & 1) {
+                    acc_h1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, whi[c], acc_h1, 0, 0, 0);
+                    acc_l1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, wlo[c], acc_l1, 0, 0, 0);
+                } else {
+                    acc_h0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, whi[c], acc_h0, 0, 0, 0);
+                    acc_l0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, wlo[c], acc_l0, 0, 0, 0);
+                }
                 __builtin_amdgcn_sched_barrier(0);
-                a_cur = a_nxt;
+                a0 = a1;
+                a1 = a2;
             }
+            const f4 acc_h = acc_h0 + acc_h1, acc_l = acc_l0 + acc_l1;
             // lane holds rows 4*gq + j of the 16x16 result: disparity index
             // k = gq*Q + 4*(b0+bb) + j of pixel n
             const int kb = gq * Q + 4 * (b0 + bb);
@@ -434,47 +520,128 @@ __global__ __launch_bounds__(kThreads) void k_fbs_mfma(Geom g, Tables tb, int nb
     }
 }
 
+__device__ __forceinline__ void load_tables(const Tables& tb, int R, unsigned char* smem, int nthreads)
+{
+    float* s = reinterpret_cast<float*>(smem);
+    for (int i = threadIdx.x; i < 256; i += nthreads) s[i] = tb.gr[i];
+    if (threadIdx.x < 32) s[256 + threadIdx.x] = (threadIdx.x <= R) ? tb.gs[threadIdx.x] : 0.0f;
+}
+
+// One workgroup per tile of one frame.
+template <int R, int CH, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fbs_mfma(TileJob job, Tables tb)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    load_tables(tb, R, smem, 64 * NW);
+    __syncthreads();
+    mfma_tile<R, CH, NW>(job, blockIdx.x, blockIdx.y, smem);
+}
+
+// Persistent workgroups over a queue of (pair, tile) items of many frames of
+// one radius / channel class.  Every workgroup pops items until the queue is
+// empty, so every wave reaches the end.
+template <int R, int CH, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __restrict__ pairs,
+                                                            const int2* __restrict__ items,
+                                                            int n_items, int* __restrict__ counter,
+                                                            const uint8_t* const* __restrict__ Ls,
+                                                            const uint8_t* const* __restrict__ Rs,
+                                                            int32_t* const* __restrict__ disps,
+                                                            float* const* __restrict__ subs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
+    constexpr int kThreads = 64 * NW;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();   // also: every wave is done with the previous tile's LDS
+        const int it = s_item;
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const BatchPair& bp = pairs[w.x];
+        load_tables(bp.tb, R, smem, kThreads);
+        __syncthreads();   // tables visible; s_item read by every wave
+        TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr};
+        mfma_tile<R, CH, NW>(job, w.y % bp.tiles_x, w.y / bp.tiles_x, smem);
+    }
+}
+
 constexpr int kLdsLimit = 64 * 1024;
 
-int pick_nb(int r, int ch, int D)
+int max_nb(int r, int ch, int D, int nw)
 {
     const int nblk = (D + 15) >> 4;
     int nb = 1;
-    while (nb < nblk && nb < 4 && mfma_layout(r, ch, D, nb + 1).bytes <= kLdsLimit) ++nb;
+    while (nb < nblk && nb < 4 && mfma_layout(r, ch, D, nb + 1, nw).bytes <= kLdsLimit) ++nb;
     return nb;
 }
 
-template <int R, int CH>
-hipError_t launch_rc(const Geom& g, const Tables& t, float scap, const uint8_t* L,
-                     const uint8_t* Rimg, int32_t* disp, float* sub, float* agg, hipStream_t s)
+template <int R, int CH, int NW>
+hipError_t launch_frame(const TileJob& job, const Tables& t, hipStream_t s)
 {
-    const int nb = pick_nb(R, CH, g.D);
-    const MfmaLayout lay = mfma_layout(R, CH, g.D, nb);
+    const MfmaLayout lay = mfma_layout(R, CH, job.g.D, job.nb, NW);
     if (lay.bytes > kLdsLimit) return hipErrorInvalidConfiguration;
-    dim3 grid((g.W + kTileW - 1) / kTileW, (g.H + kTileH - 1) / kTileH);
-    hipLaunchKernelGGL((k_fbs_mfma<R, CH>), grid, dim3(kThreads), lay.bytes, s, g, t, nb, scap, L,
-                       Rimg, disp, sub, agg);
+    dim3 grid((job.g.W + 2 * NW - 1) / (2 * NW), (job.g.H + kTileH - 1) / kTileH);
+    hipLaunchKernelGGL((k_fbs_mfma<R, CH, NW>), grid, dim3(64 * NW), lay.bytes, s, job, t);
     return hipGetLastError();
 }
 
-template <int CH>
-hipError_t launch_ch(const Geom& g, const Tables& t, float scap, const uint8_t* L,
-                     const uint8_t* R, int32_t* disp, float* sub, float* agg, hipStream_t s)
+template <int R, int CH, int NW>
+hipError_t launch_batch(const BatchClass& bc, hipStream_t s)
 {
-    switch (g.r) {
-    case 1: return launch_rc<1, CH>(g, t, scap, L, R, disp, sub, agg, s);
-    case 2: return launch_rc<2, CH>(g, t, scap, L, R, disp, sub, agg, s);
-    case 3: return launch_rc<3, CH>(g, t, scap, L, R, disp, sub, agg, s);
-    case 4: return launch_rc<4, CH>(g, t, scap, L, R, disp, sub, agg, s);
-    case 5: return launch_rc<5, CH>(g, t, scap, L, R, disp, sub, agg, s);
-    case 6: return launch_rc<6, CH>(g, t, scap, L, R, disp, sub, agg, s);
-    case 7: return launch_rc<7, CH>(g, t, scap, L, R, disp, sub, agg, s);
-    case 8: return launch_rc<8, CH>(g, t, scap, L, R, disp, sub, agg, s);
-    case 9: return launch_rc<9, CH>(g, t, scap, L, R, disp, sub, agg, s);
-    case 10: return launch_rc<10, CH>(g, t, scap, L, R, disp, sub, agg, s);
+    if (bc.lds <= 0 || bc.lds > kLdsLimit) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_fbs_mfma_batch<R, CH, NW>), dim3(bc.grid), dim3(64 * NW), bc.lds, s,
+                       bc.pairs, bc.items, bc.n_items, bc.counter, bc.L, bc.R, bc.disp, bc.sub);
+    return hipGetLastError();
+}
+
+// (R, CH, NW) dispatch; F<R, CH, NW>::run(args...)
+template <template <int, int, int> class F, int CH, int NW, typename... A>
+hipError_t dispatch_r(int r, A&&... a)
+{
+    switch (r) {
+    case 1: return F<1, CH, NW>::run(a...);
+    case 2: return F<2, CH, NW>::run(a...);
+    case 3: return F<3, CH, NW>::run(a...);
+    case 4: return F<4, CH, NW>::run(a...);
+    case 5: return F<5, CH, NW>::run(a...);
+    case 6: return F<6, CH, NW>::run(a...);
+    case 7: return F<7, CH, NW>::run(a...);
+    case 8: return F<8, CH, NW>::run(a...);
+    case 9: return F<9, CH, NW>::run(a...);
+    case 10: return F<10, CH, NW>::run(a...);
     default: return hipErrorInvalidValue;
     }
 }
+
+template <template <int, int, int> class F, typename... A>
+hipError_t dispatch(int r, int ch, int nw, A&&... a)
+{
+    if (ch == 3) return nw == 4 ? dispatch_r<F, 3, 4>(r, a...) : dispatch_r<F, 3, 8>(r, a...);
+    return nw == 4 ? dispatch_r<F, 1, 4>(r, a...) : dispatch_r<F, 1, 8>(r, a...);
+}
+
+template <int R, int CH, int NW>
+struct FrameLauncher {
+    static hipError_t run(const TileJob& j, const Tables& t, hipStream_t s)
+    {
+        return launch_frame<R, CH, NW>(j, t, s);
+    }
+};
+
+template <int R, int CH, int NW>
+struct BatchLauncher {
+    static hipError_t run(const BatchClass& bc, hipStream_t s) { return launch_batch<R, CH, NW>(bc, s); }
+};
+
+template <int R, int CH, int NW>
+struct BatchOccupancy {
+    static hipError_t run(int lds, int* blocks)
+    {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fbs_mfma_batch<R, CH, NW>,
+                                                            64 * NW, lds);
+    }
+};
 
 // Cap as the kernel sees it: tau (gray) or 3 tau (RGB), which must be an
 // exact fp16 value so every cost is exact in the A operand.
@@ -496,16 +663,49 @@ bool mfma_supported(const Geom& g)
     if (g.r < 1 || g.r > kMaxR) return false;
     if (g.C != 1 && g.C != 3) return false;
     if (!scaled_cap(g, &scap)) return false;
-    return mfma_layout(g.r, g.C, g.D, 1).bytes <= kLdsLimit;
+    return mfma_layout(g.r, g.C, g.D, 1, 8).bytes <= kLdsLimit &&
+           mfma_layout(g.r, g.C, g.D, 1, 4).bytes <= kLdsLimit;
+}
+
+float mfma_scaled_cap(const Geom& g)
+{
+    float scap = 0.0f;
+    scaled_cap(g, &scap);
+    return scap;
+}
+
+int mfma_max_nb(const Geom& g, int nw) { return max_nb(g.r, g.C, g.D, nw); }
+
+int mfma_lds_bytes(const Geom& g, int nb, int nw) { return mfma_layout(g.r, g.C, g.D, nb, nw).bytes; }
+
+hipError_t launch_mfma_cfg(const Geom& g, const Tables& t, const MfmaCfg& cfg, const uint8_t* L,
+                           const uint8_t* R, int32_t* disp, float* sub, float* agg, hipStream_t s)
+{
+    float scap;
+    if (!mfma_supported(g) || !scaled_cap(g, &scap)) return hipErrorInvalidValue;
+    if ((cfg.nw != 4 && cfg.nw != 8) || cfg.nb < 1 || cfg.nb > max_nb(g.r, g.C, g.D, cfg.nw))
+        return hipErrorInvalidValue;
+    const TileJob job{g, scap, cfg.nb, L, R, disp, sub, agg};
+    return dispatch<FrameLauncher>(g.r, g.C, cfg.nw, job, t, s);
 }
 
 hipError_t launch_mfma(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
                        int32_t* disp, float* sub, float* agg, hipStream_t s)
 {
-    float scap;
-    if (!mfma_supported(g) || !scaled_cap(g, &scap)) return hipErrorInvalidValue;
-    if (g.C == 3) return launch_ch<3>(g, t, scap, L, R, disp, sub, agg, s);
-    return launch_ch<1>(g, t, scap, L, R, disp, sub, agg, s);
+    const MfmaCfg cfg{8, max_nb(g.r, g.C, g.D, 8)};
+    return launch_mfma_cfg(g, t, cfg, L, R, disp, sub, agg, s);
+}
+
+hipError_t launch_mfma_batch(const BatchClass& bc, hipStream_t s)
+{
+    return dispatch<BatchLauncher>(bc.r, bc.ch, bc.nw, bc, s);
+}
+
+int mfma_batch_blocks_per_cu(int r, int ch, int nw, int lds_bytes)
+{
+    int blocks = 0;
+    if (dispatch<BatchOccupancy>(r, ch, nw, lds_bytes, &blocks) != hipSuccess) return 1;
+    return blocks > 0 ? blocks : 1;
 }
 
 }  // namespace fbs

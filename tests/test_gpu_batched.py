@@ -1,0 +1,152 @@
+"""Batched plans: one graph launch over many pairs of uneven sizes.
+
+The plan runs each pair through the same per-pixel arithmetic as fbs_run
+(the accumulation order depends on the radius only, never on the tuned
+waves-per-workgroup or slab depth), so its outputs must equal per-pair
+fbs_run bit for bit.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Problem
+from paper_1807_02044_amd import _lib as L
+from paper_1807_02044_amd import scenes
+import paper_1807_02044_amd as fbs
+
+from parity import compare_maps, weight_floor
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# a small uneven batch: sizes, ranges and radii differ; one RGB pair and one
+# pair the matrix cores do not take (radius 12 -> vector-ALU kernel)
+def _batch():
+    specs = [
+        (96, 72, 1, 0, 31, 5), (150, 97, 1, 3, 66, 7), (64, 48, 1, 0, 15, 10),
+        (200, 40, 3, 0, 47, 7), (77, 61, 1, 0, 20, 12), (130, 90, 1, 0, 95, 5),
+    ]
+    out = []
+    for i, (W, H, C, d0, d1, r) in enumerate(specs):
+        wl = scenes.Workload(f"b{i}", W, H, C, d0, d1, r, float(r), 10.0, 40.0,
+                             scene="slanted", seed=500 + i, n_planes=4)
+        out.append((wl, scenes.make_pair(wl)))
+    return out
+
+
+def _run_plan(plan, pairs):
+    dev = torch.device("cuda:0")
+    Ls = [torch.from_numpy(p.left).to(dev) for _, p in pairs]
+    Rs = [torch.from_numpy(p.right).to(dev) for _, p in pairs]
+    Ds = [torch.full((wl.height, wl.width), -1, dtype=torch.int32, device=dev) for wl, _ in pairs]
+    Ss = [torch.full((wl.height, wl.width), -1.0, dtype=torch.float32, device=dev) for wl, _ in pairs]
+    plan.launch(Ls, Rs, Ds, Ss)
+    torch.cuda.synchronize()
+    return Ls, Rs, [d.cpu().numpy() for d in Ds], [s.cpu().numpy() for s in Ss]
+
+
+def test_plan_equals_per_pair_run_bitwise():
+    pairs = _batch()
+    params = [fbs.params_for(wl) for wl, _ in pairs]
+    plan = L.FbsPlan(params)
+    cfgs = [plan.pair_config(i) for i in range(len(pairs))]
+    _say("configs", cfgs, "launches", plan.num_launches())
+    assert cfgs[4][0] == 0 and all(c[0] == 1 for i, c in enumerate(cfgs) if i != 4)
+    assert plan.num_launches() == 2
+    Ls, Rs, Ds, Ss = _run_plan(plan, pairs)
+    for i, (wl, _) in enumerate(pairs):
+        d, s = fbs.run(params[i], Ls[i], Rs[i])
+        np.testing.assert_array_equal(Ds[i], d.cpu().numpy(), err_msg=wl.name)
+        np.testing.assert_array_equal(Ss[i].view(np.uint32), s.cpu().numpy().view(np.uint32),
+                                      err_msg=wl.name)
+    plan.close()
+
+
+def test_plan_tuning_cache_roundtrip(tmp_path):
+    pairs = _batch()[:3]
+    params = [fbs.params_for(wl) for wl, _ in pairs]
+    cache = str(tmp_path / "tune.json")
+    plan = L.FbsPlan(params, tune_cache=cache, tune=True)
+    tuned = [plan.pair_config(i) for i in range(3)]
+    _, _, Ds, Ss = _run_plan(plan, pairs)
+    plan.close()
+    data = json.load(open(cache))
+    assert data["arch"] == "gfx950" and len(data["entries"]) == 3
+    for key, (nw, nb, us) in data["entries"].items():
+        assert nw in (4, 8) and nb >= 1 and us > 0
+    # a plan built from the cache alone picks the same configurations
+    plan2 = L.FbsPlan(params, tune_cache=cache, tune=False)
+    assert [plan2.pair_config(i) for i in range(3)] == tuned
+    _, _, Ds2, Ss2 = _run_plan(plan2, pairs)
+    for a, b in zip(Ds, Ds2):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(Ss, Ss2):
+        np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+    plan2.close()
+
+
+def test_plan_relaunch_with_new_buffers_and_oracle():
+    pairs = _batch()
+    params = [fbs.params_for(wl) for wl, _ in pairs]
+    plan = L.FbsPlan(params)
+    _run_plan(plan, pairs)                       # first launch, then fresh buffers
+    Ls, Rs, Ds, Ss = _run_plan(plan, pairs)
+    wl, pr = pairs[1]
+    pb = Problem.from_workload(wl)
+    do, so, ao = oracle.fbs(pb, pr.left, pr.right, want_agg=True)
+    rep = compare_maps(Ds[1], Ss[1], do, so, ao.reshape(ao.shape[0], -1), pb.d_min,
+                       floor=weight_floor((2 * pb.radius + 1) ** 2, pb.tau))
+    _say(rep)
+    assert rep.ok, str(rep)
+    plan.close()
+
+
+def test_plan_rejects_bad_input():
+    wl = scenes.workload("tiny")
+    p = fbs.params_for(wl)
+    plan = L.FbsPlan([p])
+    with pytest.raises(L.FbsError):
+        plan.launch([None], [None], [None], [None])
+    plan.close()
+
+
+def test_plan_class_mixing_slab_depths(tmp_path):
+    """One class (r = 10, 4 waves) holding a 64-disparity pair at slab depth 2
+    and a 96-disparity pair at depth 1: the launch must size LDS for the
+    largest per-pair layout, not for (largest D) x (deepest slab)."""
+    specs = [(80, 40, 0, 63), (120, 40, 0, 95), (130, 33, 2, 97)]
+    pairs = []
+    for i, (W, H, d0, d1) in enumerate(specs):
+        wl = scenes.Workload(f"m{i}", W, H, 1, d0, d1, 10, 10.0, 10.0, 40.0,
+                             scene="slanted", seed=700 + i, n_planes=3)
+        pairs.append((wl, scenes.make_pair(wl)))
+    cache = tmp_path / "tune.json"
+    entries = {f"{wl.width},{wl.height},1,{wl.n_disp},10": [4, 2 if wl.n_disp == 64 else 1, 1.0]
+               for wl, _ in pairs}
+    cache.write_text(json.dumps({"arch": "gfx950", "entries": entries}))
+    params = [fbs.params_for(wl) for wl, _ in pairs]
+    plan = L.FbsPlan(params, tune_cache=str(cache), tune=False)
+    cfgs = [plan.pair_config(i) for i in range(len(pairs))]
+    _say("configs", cfgs)
+    assert cfgs == [(1, 4, 2), (1, 4, 1), (1, 4, 1)]
+    Ls, Rs, Ds, Ss = _run_plan(plan, pairs)
+    for i, (wl, _) in enumerate(pairs):
+        d, s = fbs.run(params[i], Ls[i], Rs[i])
+        np.testing.assert_array_equal(Ds[i], d.cpu().numpy(), err_msg=wl.name)
+        np.testing.assert_array_equal(Ss[i].view(np.uint32), s.cpu().numpy().view(np.uint32))
+    plan.close()

@@ -1,0 +1,312 @@
+"""GPU surrogate kernels against the FP64 surrogate oracle.
+
+* features: bit-exact BF16 on synthetic aggregated volumes full of ties;
+* forward / backward: bit-exact where every float32 sum the kernels form is
+  exact (dyadic inputs and weights, checked by a magnitude certificate),
+  close to the oracle on random inputs otherwise;
+* Adam against the oracle's update;
+* the fallback gate of fbs_surrogate_run, forced both ways.
+"""
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+from paper_1807_02044_amd import _lib as L
+from paper_1807_02044_amd import scenes
+import paper_1807_02044_amd as fbs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+KEYS = ["w0", "b0", "w1", "b1", "w2", "b2", "w3", "b3"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def pack(p):
+    return np.concatenate([np.asarray(p[k], dtype=np.float32).reshape(-1) for k in KEYS])
+
+
+def unpack(flat):
+    out, o = {}, 0
+    shapes = {"w0": (3, 3, 32, 17), "b0": (32,), "w1": (3, 3, 32, 32), "b1": (32,),
+              "w2": (3, 3, 32, 32), "b2": (32,), "w3": (3, 3, 1, 32), "b3": (1,)}
+    for k in KEYS:
+        n = int(np.prod(shapes[k]))
+        out[k] = np.asarray(flat[o:o + n], dtype=np.float64).reshape(shapes[k])
+        o += n
+    assert o == flat.size
+    return out
+
+
+def bf16_bits(x):
+    """float64 array of BF16-representable values -> uint16 bit patterns."""
+    a = np.asarray(x, dtype=np.float32)
+    assert np.array_equal(S.bf16(a), a.astype(np.float64))
+    return (a.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def bits_to_f(u16):
+    return (u16.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def feat_tensor(feat17):
+    """[H][W][17] BF16-exact features -> device uint16 [H][W][32] (zero padded)."""
+    H, W, _ = feat17.shape
+    f = np.zeros((H, W, 32), dtype=np.uint16)
+    f[..., :17] = bf16_bits(feat17)
+    return torch.from_numpy(f.view(np.int16)).to(DEV)
+
+
+def dev_f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def grads_gpu(sur, feat17, cheap, label):
+    H, W, _ = feat17.shape
+    ft = feat_tensor(feat17)
+    pred = torch.empty((H, W), dtype=torch.float32, device=DEV)
+    g = torch.empty(sur.n_params, dtype=torch.float32, device=DEV)
+    loss = torch.empty(1, dtype=torch.float32, device=DEV)
+    sur.gradients(W, H, ft, dev_f32(cheap), dev_f32(label), pred, g, loss)
+    torch.cuda.synchronize()
+    return pred.cpu().numpy().astype(np.float64), g.cpu().numpy(), float(loss.item())
+
+
+def oracle_grads(feat17, params, cheap, label):
+    resid, acts, _ = S.forward(feat17, params, bf16_points=True)
+    pred = cheap + resid
+    loss, g = S.l1_loss_grad(pred, label)
+    return pred, S.backward(g, acts, params, bf16_points=True), loss
+
+
+# ------------------------------------------------------------------ features
+
+@pytest.mark.parametrize("W,H,D,tau", [(64, 4, 8, 40.0), (97, 23, 24, 40.0), (130, 37, 96, 60.0)])
+def test_features_bit_exact(W, H, D, tau):
+    rng = np.random.default_rng(W * 1000 + D)
+    # costs on a coarse grid (many exact ties), some planes constant
+    agg = (rng.integers(0, 48, size=(D, H, W)) * 0.75).astype(np.float32)
+    agg[D // 2] = 3.0
+    left = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+    sur = L.FbsSurrogate(W, H, D)
+    p = L.make_params(W, H, 1, 5, 5 + D - 1, 3, 3.0, 10.0, tau)
+    feat = torch.empty((H, W, 32), dtype=torch.int16, device=DEV)
+    sur.features(p, torch.from_numpy(left).to(DEV), dev_f32(agg), feat)
+    torch.cuda.synchronize()
+    got = feat.cpu().numpy().view(np.uint16)
+    want = S.features(agg.astype(np.float64), left, d_min=5, tau=tau)
+    np.testing.assert_array_equal(got[..., :17], bf16_bits(S.bf16(want)))
+    assert not got[..., 17:].any()
+    sur.close()
+
+
+def test_features_reject_rgb_and_small_range():
+    sur = L.FbsSurrogate(32, 8, 16)
+    feat = torch.empty((8, 32, 32), dtype=torch.int16, device=DEV)
+    agg = torch.zeros((16, 8, 32), dtype=torch.float32, device=DEV)
+    img = torch.zeros((8, 32 * 3), dtype=torch.uint8, device=DEV)
+    with pytest.raises(L.FbsError):
+        sur.features(L.make_params(32, 8, 3, 0, 15, 3, 3.0, 10.0, 40.0), img, agg, feat)
+    with pytest.raises(L.FbsError):
+        sur.features(L.make_params(32, 8, 1, 0, 6, 3, 3.0, 10.0, 40.0), img, agg, feat)
+    sur.close()
+
+
+# --------------------------------------------------------- dyadic exactness
+
+def _dyadic_case(seed, H=8, W=32):
+    rng = np.random.default_rng(seed)
+    feat = rng.integers(0, 17, size=(H, W, 17)) / 16.0           # multiples of 2^-4 in [0, 1]
+    p = {}
+    for l, (ci, co) in enumerate([(17, 32), (32, 32), (32, 32), (32, 1)]):
+        # sparse +-1/2 weights and non-positive biases keep the sums small
+        nz = rng.random((3, 3, co, ci)) < 0.1
+        p[f"w{l}"] = np.where(nz, rng.choice([-0.5, 0.5], size=(3, 3, co, ci)), 0.0)
+        p[f"b{l}"] = rng.choice([-1.0, -0.5, 0.0], size=co)
+    cheap = rng.integers(0, 64, size=(H, W)) / 4.0
+    label = cheap + rng.integers(-8, 9, size=(H, W)) / 4.0
+    return feat, p, cheap, label
+
+
+def _certify(feat, p, cheap, label):
+    """Every float32 sum formed on the GPU is exact when all its terms are
+    multiples of a unit u and the sum of their magnitudes stays below
+    2^20 u.  Units here: features 2^-4, weights and biases 2^-1, so the
+    layer-l pre-activation has unit 2^-(5+l); the loss gradient is
+    +-1/N or 0 with N a power of two."""
+    N = feat.shape[0] * feat.shape[1]
+    assert N & (N - 1) == 0
+    resid, acts, _ = S.forward(feat, p, bf16_points=True)
+    a = [np.abs(x) for x in acts]
+    for l in range(4):
+        bound = S.conv3x3(a[l], np.abs(p[f"w{l}"]), np.abs(p[f"b{l}"]))
+        assert bound.max() < 2.0 ** 20 * 2.0 ** -(5 + l), ("forward", l)
+    pred = cheap + resid
+    _, g = S.l1_loss_grad(pred, label)
+    # backward sums: data gradients and weight gradients, bounded by |g| |a| and |g| |w|
+    absp = {k: np.abs(v) for k, v in p.items()}
+    gabs = S.backward(np.abs(g), a, absp, bf16_points=True)
+    for l in range(4):
+        ua = 2.0 ** -4 if l == 0 else 2.0 ** -(4 + l)
+        ug = 2.0 ** -np.log2(N) * 2.0 ** -(3 - l)
+        assert np.abs(gabs[f"w{l}"]).max() < 2.0 ** 20 * ua * ug, ("wgrad", l)
+        assert np.abs(gabs[f"b{l}"]).max() < 2.0 ** 20 * ug, ("bgrad", l)
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_forward_backward_bit_exact_on_dyadic_inputs(seed):
+    feat, p, cheap, label = _dyadic_case(seed)
+    _certify(feat, p, cheap, label)
+    H, W, _ = feat.shape
+    sur = L.FbsSurrogate(W, H, 16)
+    sur.set_params(pack(p))
+    np.testing.assert_array_equal(sur.get_params(), pack(p))
+    want_pred, want_g, want_loss = oracle_grads(feat, p, cheap, label)
+    # forward alone
+    pred = torch.empty((H, W), dtype=torch.float32, device=DEV)
+    sur.forward(W, H, feat_tensor(feat), dev_f32(cheap), pred)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pred.cpu().numpy().astype(np.float64), want_pred)
+    # forward + backward
+    got_pred, got_g, got_loss = grads_gpu(sur, feat, cheap, label)
+    np.testing.assert_array_equal(got_pred, want_pred)
+    got = unpack(got_g)
+    for k in KEYS:
+        np.testing.assert_array_equal(got[k], want_g[k].reshape(got[k].shape), err_msg=k)
+    assert got_loss == pytest.approx(want_loss, rel=1e-6)
+    _say("dyadic", seed, "nonzero grads", {k: int(np.count_nonzero(got[k])) for k in KEYS})
+    assert all(np.count_nonzero(got[k]) > 0 for k in KEYS)
+    sur.close()
+
+
+# ----------------------------------------------------------- random inputs
+
+@pytest.mark.parametrize("H,W", [(24, 40), (37, 71)])
+def test_forward_backward_close_on_random_inputs(H, W):
+    rng = np.random.default_rng(H * W)
+    feat = S.bf16(rng.uniform(0, 1, size=(H, W, 17)))
+    p = {k: v.astype(np.float64) for k, v in S.init_params(7).items()}
+    for l in range(4):
+        p[f"b{l}"] = rng.normal(0, 0.05, p[f"b{l}"].shape).astype(np.float32).astype(np.float64)
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    cheap = rng.uniform(0, 60, size=(H, W)).astype(np.float32).astype(np.float64)
+    label = (cheap + rng.normal(0, 1, size=(H, W))).astype(np.float32).astype(np.float64)
+    sur = L.FbsSurrogate(W, H, 16)
+    sur.set_params(pack(p))
+    want_pred, want_g, want_loss = oracle_grads(feat, p, cheap, label)
+    got_pred, got_g, got_loss = grads_gpu(sur, feat, cheap, label)
+    resid = want_pred - cheap
+    err = np.abs(got_pred - want_pred)
+    _say("pred max err", err.max(), "resid scale", np.abs(resid).max())
+    # float32 sums can move a BF16 activation by one BF16 step where the
+    # exact value sits next to a rounding boundary; that rarely happens
+    assert np.quantile(err, 0.99) <= 1e-5 * (1 + np.abs(resid).max())
+    assert err.max() <= 1e-2 * (1 + np.abs(resid).max())
+    got = unpack(got_g)
+    for k in KEYS:
+        a, b = got[k].reshape(-1), want_g[k].reshape(-1)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+        rel = np.abs(a - b).max() / (np.abs(b).max() + 1e-30)
+        _say(k, "cos", cos, "rel", rel)
+        assert cos >= 0.999 and rel <= 0.05, k
+    assert got_loss == pytest.approx(want_loss, rel=1e-5)
+    sur.close()
+
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(21)
+    p = S.init_params(9)
+    sur = L.FbsSurrogate(16, 16, 16)
+    sur.set_params(pack(p))
+    state = {}
+    cur = {k: v.copy() for k, v in p.items()}
+    for step in range(3):
+        gflat = rng.normal(0, 1e-2, size=sur.n_params).astype(np.float32)
+        sur.adam(dev_f32(gflat), 1e-3)
+        cur, state = S.adam_step(cur, unpack(gflat.astype(np.float64)), state, lr=1e-3)
+    torch.cuda.synchronize()
+    got = sur.get_params()
+    want = pack(cur)
+    assert np.abs(got - want).max() <= 1e-6
+    assert np.abs(got - pack(p)).max() > 1e-3
+    sur.close()
+
+
+def test_set_params_rejects_wrong_size():
+    sur = L.FbsSurrogate(16, 16, 16)
+    with pytest.raises(L.FbsError):
+        sur.set_params(np.zeros(10, dtype=np.float32))
+    with pytest.raises(L.FbsError):
+        sur.forward(17, 16, torch.zeros((16, 17, 32), dtype=torch.int16, device=DEV),
+                    torch.zeros((16, 17), device=DEV), torch.zeros((16, 17), device=DEV))
+    sur.close()
+
+
+# ------------------------------------------------------------ gated run
+
+def _pair(W=96, H=64, D=24, seed=31):
+    wl = scenes.Workload("sur", W, H, 1, 0, D - 1, 3, 3.0, 10.0, 40.0, scene="slanted",
+                         seed=seed, n_planes=4)
+    pr = scenes.make_pair(wl)
+    cheap = fbs.params_for(wl)
+    full = fbs.params_for(wl.with_(radius=6, sigma_s=6.0))
+    return wl, pr, cheap, full
+
+
+def test_run_gate_forced_both_ways():
+    wl, pr, cheap, full = _pair()
+    W, H, D = wl.width, wl.height, wl.n_disp
+    Lt, Rt = torch.from_numpy(pr.left).to(DEV), torch.from_numpy(pr.right).to(DEV)
+    sur = L.FbsSurrogate(W, H, D)
+    sur.set_params(pack(S.init_params(3)))
+    out = torch.full((H, W), -7.0, dtype=torch.float32, device=DEV)
+    # gate never fires: equals cheap run -> features -> forward done step by step
+    assert sur.run(cheap, full, Lt, Rt, out, 1e9, 1.0) is False
+    agg = torch.empty((D, H, W), dtype=torch.float32, device=DEV)
+    sub = torch.empty((H, W), dtype=torch.float32, device=DEV)
+    L.fbs_run(cheap, Lt, Rt, None, sub, agg)
+    feat = torch.empty((H, W, 32), dtype=torch.int16, device=DEV)
+    sur.features(cheap, Lt, agg, feat)
+    pred = torch.empty((H, W), dtype=torch.float32, device=DEV)
+    sur.forward(W, H, feat, sub, pred)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), pred.cpu().numpy())
+    # gate always fires (any pixel off by more than 0 px): equals the full run
+    assert sur.run(cheap, full, Lt, Rt, out, 0.0, 0.0) is True
+    _, full_sub = fbs.run(full, Lt, Rt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), full_sub.cpu().numpy())
+    # mismatched pair descriptions are rejected
+    with pytest.raises(L.FbsError):
+        sur.run(cheap, fbs.params_for(wl.with_(d_max=D)), Lt, Rt, out, 1.0, 0.05)
+    sur.close()
+
+
+# ------------------------------------------------------- trained network
+
+def test_trained_net_gains_over_cheap_run():
+    """The committed weights, on held-out seeds, beat the cheap run alone
+    against the full-radius run (the method without the net)."""
+    import os
+    from paper_1807_02044_amd import surrogate as SG
+    if not os.path.exists(SG.WEIGHTS):
+        pytest.skip("no trained weights committed")
+    seeds = [SG.EVAL_SEED0 + i for i in range(3)]
+    cw, _ = SG.workloads(seeds[0])
+    sur = L.FbsSurrogate(cw.width, cw.height, cw.n_disp)
+    sur.set_params(np.load(SG.WEIGHTS))
+    data = SG.Dataset(sur, seeds, torch.device(DEV), workers=3, log=_say)
+    ev = SG.evaluate(sur, data, torch.device(DEV))
+    _say({k: np.round(v, 4).tolist() for k, v in ev.items() if k != "frames"})
+    assert np.mean(ev["bad1_net"]) < np.mean(ev["bad1_cheap"])
+    assert np.mean(ev["mae_net"]) < np.mean(ev["mae_cheap"])
+    sur.close()
