@@ -171,7 +171,7 @@ struct TileJob {
 // and synchronised the workgroup.
 template <int R, int CH, int NW>
 __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int tile_y,
-                                          unsigned char* smem)
+                                          unsigned char* smem, int tid)
 {
     constexpr int kThreads = 64 * NW, kTileW = 2 * NW;
     const Geom& g = job.g;
@@ -201,7 +201,6 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     uint8_t* s_R = smem + lay.off_R;
     _Float16* s_cost = reinterpret_cast<_Float16*>(smem + lay.off_cost);
 
-    const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int X0 = tile_x * kTileW, Y0 = tile_y * kTileH;
     const int ox = X0 - R, oy = Y0 - R;           // image position of LDS tile (0,0)
@@ -534,7 +533,7 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma(TileJob job, Tables tb)
     extern __shared__ __align__(16) unsigned char smem[];
     load_tables(tb, R, smem, 64 * NW);
     __syncthreads();
-    mfma_tile<R, CH, NW>(job, blockIdx.x, blockIdx.y, smem);
+    mfma_tile<R, CH, NW>(job, blockIdx.x, blockIdx.y, smem, threadIdx.x);
 }
 
 // Persistent workgroups over a queue of (pair, tile) items of many frames of
@@ -555,14 +554,21 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __r
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();   // also: every wave is done with the previous tile's LDS
-        const int it = s_item;
+        // uniform across the workgroup: keep the item, its pair and geometry
+        // in scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= n_items) break;
         const int2 w = items[it];
         const BatchPair& bp = pairs[w.x];
         load_tables(bp.tb, R, smem, kThreads);
         __syncthreads();   // tables visible; s_item read by every wave
         TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr};
-        mfma_tile<R, CH, NW>(job, w.y % bp.tiles_x, w.y / bp.tiles_x, smem);
+        // an opaque copy of the thread index per item keeps the compiler from
+        // hoisting the tile's index arithmetic out of the loop (it would stay
+        // live in registers across every item)
+        int tid;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+        mfma_tile<R, CH, NW>(job, w.y % bp.tiles_x, w.y / bp.tiles_x, smem, tid);
     }
 }
 
