@@ -41,6 +41,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kTileH = 8;         // tile rows; a tile is kTileH x (2 * waves) pixels
 constexpr float kWScale = 16384.0f;  // 2^14: keeps small weights in fp16's normal range
 constexpr int kMaxR = 10;
+// range factor by signed intensity difference -255..255 (no abs per weight),
+// padded to a multiple of 4 floats
+constexpr int kLutN = 512;
 
 constexpr int n_chunks(int gh, int gw, int r) { return (((gh + 2 * r) * ((gw + 2 * r + 7) / 8)) + 3) / 4; }
 
@@ -91,7 +94,7 @@ __host__ __device__ constexpr MfmaLayout mfma_layout(int r, int ch, int D, int n
     m.lwb = ch * c.LW;
     // +16: slack for the unaligned reads of the last octet of a row
     m.rwb = (ch * (c.LW + D - 1) + 16 + 3) & ~3;
-    m.off_wx = (256 + 32) * 4;  // after the range LUT and the spatial factors
+    m.off_wx = (kLutN + 32) * 4;  // after the signed range LUT and the spatial factors
     m.off_wy = m.off_wx + tile_w * c.LW * 4;
     m.off_L = m.off_wy + align16(kTileH * c.LH * 4);
     m.off_R = m.off_L + align16(c.LH * m.lwb);
@@ -166,9 +169,9 @@ struct TileJob {
     float* agg;
 };
 
-// The caller has put the range LUT (256 floats) at smem[0] and the spatial
-// factors exp(-k^2/gd^2), k = 0..31 (0 beyond the radius), right after it,
-// and synchronised the workgroup.
+// The caller has put the range LUT by signed difference (kLutN floats, entry
+// 255 + dI) at smem[0] and the spatial factors exp(-k^2/gd^2), k = 0..31 (0
+// beyond the radius), right after it, and synchronised the workgroup.
 template <int R, int CH, int NW>
 __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int tile_y,
                                           unsigned char* smem, int tid)
@@ -193,8 +196,8 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     const int Q = nblk * 4;           // disparities per lane group
     const MfmaLayout lay = mfma_layout(R, CH, D, nb, NW);
     const int RWB = lay.rwb;
-    const float* s_gr = reinterpret_cast<const float*>(smem);
-    const float* s_gs = s_gr + 256;
+    const float* s_gr = reinterpret_cast<const float*>(smem) + 255;  // index by I_q - I_p
+    const float* s_gs = s_gr - 255 + kLutN;
     float* s_wx = reinterpret_cast<float*>(smem + lay.off_wx);
     float* s_wy = reinterpret_cast<float*>(smem + lay.off_wy);
     uint8_t* s_L = smem + lay.off_L;
@@ -285,7 +288,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
             for (int ch = 0; ch < CH; ++ch) {
                 const int b = CH * j + ch;
                 const int iv = (int)((lq[b >> 2] >> (8 * (b & 3))) & 0xffu);
-                const float f = s_gr[abs(iv - (int)lp[ch])];
+                const float f = s_gr[iv - (int)lp[ch]];
                 wr = ch == 0 ? f : wr * f;
             }
             w[j] = (wx[j] * wy) * wr;
@@ -522,8 +525,8 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
 __device__ __forceinline__ void load_tables(const Tables& tb, int R, unsigned char* smem, int nthreads)
 {
     float* s = reinterpret_cast<float*>(smem);
-    for (int i = threadIdx.x; i < 256; i += nthreads) s[i] = tb.gr[i];
-    if (threadIdx.x < 32) s[256 + threadIdx.x] = (threadIdx.x <= R) ? tb.gs[threadIdx.x] : 0.0f;
+    for (int i = threadIdx.x; i < kLutN; i += nthreads) s[i] = i < 511 ? tb.gr[abs(i - 255)] : 0.0f;
+    if (threadIdx.x < 32) s[kLutN + threadIdx.x] = (threadIdx.x <= R) ? tb.gs[threadIdx.x] : 0.0f;
 }
 
 // One workgroup per tile of one frame.

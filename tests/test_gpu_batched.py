@@ -125,25 +125,43 @@ def test_plan_rejects_bad_input():
     plan.close()
 
 
+def _max_nb(params, wl, tmp_path, nw):
+    """Deepest slab the library accepts for one pair at `nw` waves (probed
+    through single-pair plans built from a cache entry)."""
+    best = 0
+    for nb in (1, 2, 3, 4):
+        cache = tmp_path / f"probe_{wl.name}_{nb}.json"
+        key = f"{wl.width},{wl.height},1,{wl.n_disp},{wl.radius}"
+        cache.write_text(json.dumps({"arch": "gfx950", "entries": {key: [nw, nb, 1.0]}}))
+        plan = L.FbsPlan([params], tune_cache=str(cache), tune=False)
+        if plan.pair_config(0) == (1, nw, nb):
+            best = nb
+        plan.close()
+    return best
+
+
 def test_plan_class_mixing_slab_depths(tmp_path):
-    """One class (r = 10, 4 waves) holding a 64-disparity pair at slab depth 2
-    and a 96-disparity pair at depth 1: the launch must size LDS for the
+    """One class (r = 10, 4 waves) holding a 32-disparity pair at its deepest
+    slab and a 96-disparity pair at depth 1: the launch must size LDS for the
     largest per-pair layout, not for (largest D) x (deepest slab)."""
-    specs = [(80, 40, 0, 63), (120, 40, 0, 95), (130, 33, 2, 97)]
+    specs = [(80, 40, 0, 31), (120, 40, 0, 95), (130, 33, 2, 97)]
     pairs = []
     for i, (W, H, d0, d1) in enumerate(specs):
         wl = scenes.Workload(f"m{i}", W, H, 1, d0, d1, 10, 10.0, 10.0, 40.0,
                              scene="slanted", seed=700 + i, n_planes=3)
         pairs.append((wl, scenes.make_pair(wl)))
-    cache = tmp_path / "tune.json"
-    entries = {f"{wl.width},{wl.height},1,{wl.n_disp},10": [4, 2 if wl.n_disp == 64 else 1, 1.0]
-               for wl, _ in pairs}
-    cache.write_text(json.dumps({"arch": "gfx950", "entries": entries}))
     params = [fbs.params_for(wl) for wl, _ in pairs]
+    nbs = [_max_nb(p, wl, tmp_path, 4) for p, (wl, _) in zip(params, pairs)]
+    _say("deepest slabs at 4 waves", nbs)
+    assert nbs[0] > nbs[1] >= 1 and nbs[2] >= 1
+    cache = tmp_path / "tune.json"
+    entries = {f"{wl.width},{wl.height},1,{wl.n_disp},10": [4, nb, 1.0]
+               for (wl, _), nb in zip(pairs, nbs)}
+    cache.write_text(json.dumps({"arch": "gfx950", "entries": entries}))
     plan = L.FbsPlan(params, tune_cache=str(cache), tune=False)
     cfgs = [plan.pair_config(i) for i in range(len(pairs))]
     _say("configs", cfgs)
-    assert cfgs == [(1, 4, 2), (1, 4, 1), (1, 4, 1)]
+    assert cfgs == [(1, 4, nb) for nb in nbs]
     Ls, Rs, Ds, Ss = _run_plan(plan, pairs)
     for i, (wl, _) in enumerate(pairs):
         d, s = fbs.run(params[i], Ls[i], Rs[i])
