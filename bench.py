@@ -132,6 +132,13 @@ def batched(args, dev):
 
     ms_graph = timed(graph)
     ms_seq = timed(sequential)
+    plan_pt = L.FbsPlan(params, tune_cache=args.tune_cache, per_tile=True)
+
+    def graph_per_tile():
+        plan_pt.launch(Ls, Rs, Ds, Ss, stream)
+
+    ms_graph_pt = timed(graph_per_tile)
+    plan_pt.close()
     cfgs = [plan.pair_config(i) for i in range(len(wls))]
     launches = plan.num_launches()
     plan.close()
@@ -144,6 +151,7 @@ def batched(args, dev):
         "gpix_disp_tap_per_s_graph": taps / (ms_graph * 1e-3) / 1e9,
         "gpix_disp_tap_per_s_sequential": taps / (ms_seq * 1e-3) / 1e9,
         "speedup": ms_seq / ms_graph, "host_launches_graph": launches,
+        "per_tile_graph_ms": ms_graph_pt, "per_tile_speedup": ms_seq / ms_graph_pt,
         "host_launches_sequential": n,
         "waves_per_wg": sorted({c[1] for c in cfgs}), "slab_blocks": sorted({c[2] for c in cfgs}),
         "scene_gen_s": gen_s, "plan_create_s": plan_s,
@@ -181,7 +189,6 @@ def surrogate(args, dev):
     n = len(seeds)
     plain = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(n)]
     out = torch.empty((H, W), dtype=torch.float32, device=dev)
-    vol = torch.empty((D, H, W), dtype=torch.float32, device=dev)
     cheap = torch.empty((H, W), dtype=torch.float32, device=dev)
     feat = torch.empty((H, W, 32), dtype=torch.int16, device=dev)
 
@@ -200,8 +207,7 @@ def surrogate(args, dev):
         L.fbs_run(pf, Ls[i], Rs[i], None, plain[i], None, None, stream)
 
     def run_net(i):
-        L.fbs_run(pc, Ls[i], Rs[i], None, cheap, vol, None, stream)
-        sur.features(pc, Ls[i], vol, feat, stream)
+        sur.cheap_run(pc, Ls[i], Rs[i], cheap, feat, stream)
         sur.forward(W, H, feat, cheap, out, stream)
 
     fb = {}

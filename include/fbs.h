@@ -135,21 +135,27 @@ int fbs_run_variant(const fbs_params* p);
 
 typedef struct fbs_plan fbs_plan;
 
+/* fbs_plan_create flags */
+#define FBS_PLAN_TUNE 0x1u     /* time candidates for shapes missing from the cache */
+#define FBS_PLAN_PER_TILE 0x2u /* one workgroup per (pair, tile) item instead of
+                                  persistent workgroups draining a queue */
+
 /* Builds a plan for n pairs (params is a HOST array of n fbs_params; every
  * pair TAD).  Each pair gets the matrix-core kernel where fbs_run would use
  * it, with its waves-per-workgroup and disparity-slab depth taken from the
- * tuning cache at tune_cache_path (JSON, may be NULL), or - when tune is
- * nonzero and the cache has no entry for the pair's (W, H, C, D, r) - by
+ * tuning cache at tune_cache_path (JSON, may be NULL), or - with
+ * FBS_PLAN_TUNE and no cache entry for the pair's (W, H, C, D, r) - by
  * timing every candidate on synthetic data of that shape (the cache file is
  * then rewritten), else from the same heuristic as fbs_run.  Pairs of equal
- * radius, channels and waves share one persistent kernel that pulls
- * (pair, tile) items from a work queue; the whole launch sequence is
+ * radius, channels and waves share one launch over their (pair, tile) items:
+ * persistent workgroups pulling items from a work queue, or with
+ * FBS_PLAN_PER_TILE one workgroup per item; the whole launch sequence is
  * captured once into a hipGraph.  Allocates device and pinned host memory
  * and synchronises the device (tuning); not for the hot path.  *out is NULL
  * on failure.  The per-pixel arithmetic equals fbs_run's, so results are
  * bit-identical to n separate fbs_run calls. */
 fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
-                           const char* tune_cache_path, int32_t tune);
+                           const char* tune_cache_path, uint32_t flags);
 
 /* Runs the plan: left, right, disp, disp_sub are HOST arrays of n DEVICE
  * pointers (images as described by the pair's params; dense int32 / float32
@@ -161,8 +167,8 @@ fbs_status fbs_plan_launch(fbs_plan* plan, const uint8_t* const* left,
                            float* const* disp_sub, void* stream);
 
 /* Configuration chosen for one pair: matrix_cores (1/0), waves per
- * workgroup (4 or 8) and disparity-slab depth in blocks of 16 (0 for a
- * vector-ALU pair).  Any output may be NULL. */
+ * workgroup (4, 8 or 12; 12 only up to radius 7) and disparity-slab depth in
+ * blocks of 16 (0 for a vector-ALU pair).  Any output may be NULL. */
 fbs_status fbs_plan_pair_config(const fbs_plan* plan, int32_t pair, int32_t* matrix_cores,
                                 int32_t* waves, int32_t* slab_blocks);
 
@@ -215,6 +221,16 @@ fbs_status fbs_surrogate_get_params(fbs_surrogate* s, float* host_params);
 fbs_status fbs_surrogate_features(fbs_surrogate* s, const fbs_params* cheap, const uint8_t* left,
                                   const float* agg, uint16_t* feat, void* stream);
 
+/* The cheap run and its features in one call: cheap_sub[H][W] receives the
+ * cheap run's subpixel map (as fbs_run), feat [H][W][32] its features (as
+ * fbs_surrogate_features on fbs_run's agg_out), bit for bit.  Where the
+ * matrix-core kernel applies this is one launch that keeps the volume out of
+ * HBM; otherwise fbs_run plus fbs_surrogate_features through the object's
+ * volume buffer (D <= max_disp). */
+fbs_status fbs_surrogate_cheap_run(fbs_surrogate* s, const fbs_params* cheap, const uint8_t* left,
+                                   const uint8_t* right, float* cheap_sub, uint16_t* feat,
+                                   void* stream);
+
 /* Prediction: pred[H][W] = cheap_sub + net(feat). */
 fbs_status fbs_surrogate_forward(fbs_surrogate* s, int32_t width, int32_t height,
                                  const uint16_t* feat, const float* cheap_sub, float* pred,
@@ -232,8 +248,8 @@ fbs_status fbs_surrogate_gradients(fbs_surrogate* s, int32_t width, int32_t heig
 /* One Adam step with learning rate lr on the master weights (device grads). */
 fbs_status fbs_surrogate_adam(fbs_surrogate* s, const float* grads, float lr, void* stream);
 
-/* Inference with fallback: runs `cheap` (fbs_run, aggregated volume kept in
- * the object), the features and the net into disp_sub; counts pixels where
+/* Inference with fallback: runs `cheap` and its features
+ * (fbs_surrogate_cheap_run) and the net into disp_sub; counts pixels where
  * the prediction and the cheap subpixel map differ by more than gate_px, and
  * when that count exceeds gate_frac * W * H reruns `full` (same pair and
  * disparity range, e.g. the full radius) into disp_sub and sets *fell_back

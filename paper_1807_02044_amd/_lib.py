@@ -31,13 +31,17 @@ FBS_MAX_DISP = 1024
 
 FBS_F_FORCE_VALU = 0x1
 
+FBS_PLAN_TUNE = 0x1
+FBS_PLAN_PER_TILE = 0x2
+
 # Entry points declared in include/fbs.h (checked by the ABI tests).
 EXPORTS = (
     "fbs_validate", "fbs_workspace_bytes", "fbs_cost", "fbs_aggregate", "fbs_wta_subpixel",
     "fbs_run", "fbs_run_variant", "fbs_plan_create", "fbs_plan_launch", "fbs_plan_pair_config",
     "fbs_plan_num_launches", "fbs_plan_destroy", "fbs_surrogate_num_params",
     "fbs_surrogate_create", "fbs_surrogate_destroy", "fbs_surrogate_set_params",
-    "fbs_surrogate_get_params", "fbs_surrogate_features", "fbs_surrogate_forward",
+    "fbs_surrogate_get_params", "fbs_surrogate_features", "fbs_surrogate_cheap_run",
+    "fbs_surrogate_forward",
     "fbs_surrogate_gradients", "fbs_surrogate_adam", "fbs_surrogate_run", "fbs_status_str",
     "fbs_last_error", "fbs_version",
 )
@@ -99,7 +103,7 @@ def lib() -> ctypes.CDLL:
             f.restype = ctypes.c_int
         pp = ctypes.POINTER(ctypes.c_void_p)
         h.fbs_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, P,
-                                      ctypes.c_char_p, ctypes.c_int32]
+                                      ctypes.c_char_p, ctypes.c_uint32]
         h.fbs_plan_create.restype = ctypes.c_int
         h.fbs_plan_launch.argtypes = [vp, pp, pp, pp, pp, vp]
         h.fbs_plan_launch.restype = ctypes.c_int
@@ -121,6 +125,7 @@ def lib() -> ctypes.CDLL:
         h.fbs_surrogate_set_params.argtypes = [vp, fp]
         h.fbs_surrogate_get_params.argtypes = [vp, fp]
         h.fbs_surrogate_features.argtypes = [vp, P, vp, vp, vp, vp]
+        h.fbs_surrogate_cheap_run.argtypes = [vp, P, vp, vp, vp, vp, vp]
         h.fbs_surrogate_forward.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
         h.fbs_surrogate_gradients.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
                                               vp, vp, vp, vp]
@@ -129,6 +134,7 @@ def lib() -> ctypes.CDLL:
                                         ctypes.POINTER(ctypes.c_int32), vp]
         for f in (h.fbs_surrogate_create, h.fbs_surrogate_set_params,
                   h.fbs_surrogate_get_params, h.fbs_surrogate_features,
+                  h.fbs_surrogate_cheap_run,
                   h.fbs_surrogate_forward, h.fbs_surrogate_gradients, h.fbs_surrogate_adam,
                   h.fbs_surrogate_run):
             f.restype = ctypes.c_int
@@ -220,11 +226,13 @@ def fbs_version() -> str:
 class FbsPlan:
     """Batched plan (fbs_plan_create / fbs_plan_launch / fbs_plan_destroy)."""
 
-    def __init__(self, params, tune_cache: Optional[str] = None, tune: bool = False):
+    def __init__(self, params, tune_cache: Optional[str] = None, tune: bool = False,
+                 per_tile: bool = False):
         arr = (FbsParams * len(params))(*params)
         h = ctypes.c_void_p(None)
         path = tune_cache.encode() if tune_cache else None
-        _check(lib().fbs_plan_create(ctypes.byref(h), len(params), arr, path, int(bool(tune))))
+        flags = (FBS_PLAN_TUNE if tune else 0) | (FBS_PLAN_PER_TILE if per_tile else 0)
+        _check(lib().fbs_plan_create(ctypes.byref(h), len(params), arr, path, flags))
         self.handle = h
         self.n = len(params)
 
@@ -288,6 +296,11 @@ class FbsSurrogate:
     def features(self, cheap: FbsParams, left, agg, feat, stream=None):
         _check(lib().fbs_surrogate_features(self.handle, ctypes.byref(cheap), _ptr(left),
                                             _ptr(agg), _ptr(feat), _stream(stream)))
+
+    def cheap_run(self, cheap: FbsParams, left, right, cheap_sub, feat, stream=None):
+        _check(lib().fbs_surrogate_cheap_run(self.handle, ctypes.byref(cheap), _ptr(left),
+                                             _ptr(right), _ptr(cheap_sub), _ptr(feat),
+                                             _stream(stream)))
 
     def forward(self, width: int, height: int, feat, cheap_sub, pred, stream=None):
         _check(lib().fbs_surrogate_forward(self.handle, width, height, _ptr(feat),

@@ -59,6 +59,13 @@ struct MfmaCfg {
 bool mfma_supported(const Geom& g);
 float mfma_scaled_cap(const Geom& g);
 int mfma_max_nb(const Geom& g, int nw);
+bool mfma_nw_valid(const Geom& g, int nw);   // 4, 8 or 12 waves and the layout fits
+MfmaCfg mfma_default_cfg(const Geom& g);     // what fbs_run uses
+// Gray TAD frame with the learned surrogate's features (D >= 8): sub map and
+// feat [H][W][32] BF16, equal to fbs_run's sub and to the features of its
+// agg_out.
+hipError_t launch_mfma_features(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
+                                float* sub, uint16_t* feat, hipStream_t s);
 int mfma_lds_bytes(const Geom& g, int nb, int nw);
 hipError_t launch_mfma(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
                        int32_t* disp, float* sub, float* agg, hipStream_t s);
@@ -81,7 +88,8 @@ struct BatchPair {
 struct BatchClass {
     int r, ch, nw;
     int lds;  // dynamic LDS bytes: the largest layout of any pair in the class
-    int grid;
+    int grid;             // persistent workgroups
+    int one_wg_per_item;  // 1: one workgroup per item instead of persistent ones
     const BatchPair* pairs;
     const int2* items;
     int n_items;

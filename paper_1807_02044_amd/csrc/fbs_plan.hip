@@ -145,7 +145,7 @@ fbs_status tune_shape(const fbs_params& p, TuneEntry* out)
         (void)hipMemcpy(L, host.data(), img, hipMemcpyHostToDevice);
         (void)hipMemcpy(R, host.data(), img, hipMemcpyHostToDevice);
         out->us = 1e30;
-        for (int nw : {4, 8}) {
+        for (int nw : {4, 8, 12}) {
             const int nbmax = fbs::mfma_max_nb(g, nw);
             for (int nb = 1; nb <= nbmax; ++nb) {
                 const fbs::MfmaCfg c{nw, nb};
@@ -194,7 +194,7 @@ void release(fbs_plan* p)
 extern "C" {
 
 fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
-                           const char* tune_cache_path, int32_t tune)
+                           const char* tune_cache_path, uint32_t flags)
 {
     using namespace fbs;
     if (!out) return api_fail(FBS_E_INVALID, "out is NULL");
@@ -225,10 +225,10 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
         p->mfma[i] = 1;
         const std::string key = shape_key(g);
         auto it = cache.find(key);
-        if (it != cache.end() && (it->second.nw == 4 || it->second.nw == 8) &&
+        if (it != cache.end() && mfma_nw_valid(g, it->second.nw) &&
             it->second.nb >= 1 && it->second.nb <= mfma_max_nb(g, it->second.nw)) {
             p->cfg[i] = MfmaCfg{it->second.nw, it->second.nb};
-        } else if (tune) {
+        } else if (flags & FBS_PLAN_TUNE) {
             TuneEntry e{};
             fbs_status st = tune_shape(params[i], &e);
             if (st != FBS_OK) {
@@ -239,7 +239,7 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
             cache_dirty = true;
             p->cfg[i] = MfmaCfg{e.nw, e.nb};
         } else {
-            p->cfg[i] = MfmaCfg{8, mfma_max_nb(g, 8)};
+            p->cfg[i] = mfma_default_cfg(g);
         }
     }
     if (cache_dirty) write_cache(tune_cache_path, cache);
@@ -313,6 +313,7 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
         bc.lds = sp.lds;
         const int per_cu = mfma_batch_blocks_per_cu(sp.r, sp.ch, sp.nw, sp.lds);
         bc.grid = std::max(1, std::min(sp.count, cus * per_cu));
+        bc.one_wg_per_item = (flags & FBS_PLAN_PER_TILE) ? 1 : 0;
         bc.pairs = p->d_pairs;
         bc.items = p->d_items + sp.first;
         bc.n_items = sp.count;

@@ -205,6 +205,34 @@ fbs_status fbs_surrogate_features(fbs_surrogate* s, const fbs_params* cheap, con
                  "surrogate features");
 }
 
+fbs_status fbs_surrogate_cheap_run(fbs_surrogate* s, const fbs_params* cheap, const uint8_t* left,
+                                   const uint8_t* right, float* cheap_sub, uint16_t* feat,
+                                   void* stream)
+{
+    fbs_status st = fbs::api_check_params(cheap);
+    if (st != FBS_OK) return st;
+    st = check_frame(s, cheap->width, cheap->height);
+    if (st != FBS_OK) return st;
+    const int D = cheap->d_max - cheap->d_min + 1;
+    if (cheap->channels != 1 || cheap->cost_type != FBS_COST_TAD || D < SUR_TOPK)
+        return api_fail(FBS_E_UNSUPPORTED, "features need a gray TAD run with >= %d disparities", SUR_TOPK);
+    if (!left || !right || !cheap_sub || !feat)
+        return api_fail(FBS_E_INVALID, "left, right, cheap_sub and feat are required");
+    if (((uintptr_t)feat & 15u) || ((uintptr_t)cheap_sub & 3u))
+        return api_fail(FBS_E_INVALID, "feat must be 16-byte and cheap_sub 4-byte aligned");
+    const fbs::Geom g = fbs::api_geom(cheap);
+    if (!(cheap->flags & FBS_F_FORCE_VALU) && fbs::mfma_supported(g)) {
+        (void)hipGetLastError();
+        return hipst(fbs::launch_mfma_features(g, fbs::api_tables(cheap), left, right, cheap_sub,
+                                               feat, (hipStream_t)stream),
+                     "surrogate cheap run");
+    }
+    if (D > s->max_d) return api_fail(FBS_E_INVALID, "%d disparities above the maximum %d", D, s->max_d);
+    st = fbs_run(cheap, left, right, nullptr, cheap_sub, s->vol, nullptr, stream);
+    if (st == FBS_OK) st = fbs_surrogate_features(s, cheap, left, s->vol, feat, stream);
+    return st;
+}
+
 fbs_status fbs_surrogate_forward(fbs_surrogate* s, int32_t width, int32_t height,
                                  const uint16_t* feat, const float* cheap_sub, float* pred,
                                  void* stream)
@@ -284,8 +312,7 @@ fbs_status fbs_surrogate_run(fbs_surrogate* s, const fbs_params* cheap, const fb
     if (!left || !right || !disp_sub) return api_fail(FBS_E_INVALID, "left, right, disp_sub required");
     if (!(gate_px >= 0.0f) || !(gate_frac >= 0.0f)) return api_fail(FBS_E_INVALID, "bad gate");
     hipStream_t q = (hipStream_t)stream;
-    st = fbs_run(cheap, left, right, nullptr, s->cheap, s->vol, nullptr, stream);
-    if (st == FBS_OK) st = fbs_surrogate_features(s, cheap, left, s->vol, s->feat, stream);
+    st = fbs_surrogate_cheap_run(s, cheap, left, right, s->cheap, s->feat, stream);
     if (st != FBS_OK) return st;
     (void)hipGetLastError();
     st = forward(s, W, H, s->feat, s->cheap, disp_sub, nullptr, q);

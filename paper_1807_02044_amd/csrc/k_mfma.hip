@@ -27,6 +27,9 @@
 // sees one contiguous quarter of the disparity range in ascending order and
 // keeps a running first-minimum WTA with the Eq. 10 neighbours; the four
 // quarters are merged with lane shuffles at the end.
+#include <algorithm>
+#include <atomic>
+
 #include "fbs_device.h"
 #include "fbs_internal.h"
 
@@ -167,12 +170,27 @@ struct TileJob {
     int32_t* disp;
     float* sub;
     float* agg;
+    uint16_t* feat;  // FEAT tiles only: learned-surrogate features [H][W][32] BF16
 };
 
 // The caller has put the range LUT by signed difference (kLutN floats, entry
 // 255 + dI) at smem[0] and the spatial factors exp(-k^2/gd^2), k = 0..31 (0
 // beyond the radius), right after it, and synchronised the workgroup.
-template <int R, int CH, int NW>
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// FEAT: besides the maps, write the learned surrogate's input features of
+// each pixel: the 8 lowest aggregated costs (ascending, ties to the lower d)
+// over the cost cap, their indices (d - d_min) / (D - 1), and the left
+// intensity / 255, as BF16 in 32 channels (the rest zero).  The aggregated
+// cost is formed exactly as for agg_out, so the features equal those of
+// fbs_surrogate_features applied to agg_out bit for bit.
+template <int R, int CH, int NW, bool FEAT = false>
 __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int tile_y,
                                           unsigned char* smem, int tid)
 {
@@ -314,7 +332,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     }
     float den = 0.0f;
     const float inv_scale = 1.0f / (CH == 3 ? 3.0f : 1.0f);
-    if (agg) {
+    if (FEAT || agg) {
         // Eq. 6's denominator: an all-ones A operand sums each weight column,
         // giving sum_q (hi + lo)(p, q) for pixel p in every lane of that pixel
         h8 ones;
@@ -334,6 +352,16 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     float best = kInf, cm = kInf, cp = kInf, prev = kInf, first_v = kInf, last_v = kInf;
     int bi = -1;
     bool need_cp = false;
+    // FEAT: this lane's 8 lowest aggregated costs of its quarter, ascending
+    float tv[FEAT ? 8 : 1];
+    int tk[FEAT ? 8 : 1];
+    if constexpr (FEAT) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            tv[i] = kInf;
+            tk[i] = 0;
+        }
+    }
 
     // Offset (halves) of octet 4c + gq of the group's union within a plane.
     // It is periodic in c with period P = lcm(4, OPR) / 4 chunks (P chunks
@@ -479,6 +507,23 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
                     prev = v;
                     if (agg && pin)
                         agg[(size_t)k * g.W * g.H + (size_t)py * g.W + px] = (v / den) * inv_scale;
+                    if constexpr (FEAT) {
+                        // k rises within a quarter: insert after equal values
+                        const float a = (v / den) * inv_scale;
+                        if (a < tv[7]) {
+#pragma unroll
+                            for (int i = 7; i >= 0; --i) {
+                                const bool shift = i > 0 && a < tv[i > 0 ? i - 1 : 0];
+                                if (shift) {
+                                    tv[i] = tv[i - 1];
+                                    tk[i] = tk[i - 1];
+                                } else if (a < tv[i]) {
+                                    tv[i] = a;
+                                    tk[i] = k;
+                                }
+                            }
+                        }
+                    }
                 }
             }
         }
@@ -520,6 +565,51 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
         if (disp) disp[o] = g.dmin + wk;
         if (sub) sub[o] = ds;
     }
+    if constexpr (FEAT) {
+        // merge the four quarters' sorted lists: 8 rounds, each taking the
+        // smallest head (the lower quarter, hence the lower d, on a tie)
+        uint32_t fw[8];
+        const float dn = (float)(D - 1);
+#pragma unroll
+        for (int rnd = 0; rnd < 8; ++rnd) {
+            float bvv = __shfl(tv[0], n);
+            int bkk = __shfl(tk[0], n), bt = 0;
+#pragma unroll
+            for (int t = 1; t < 4; ++t) {
+                const float v = __shfl(tv[0], n + 16 * t);
+                const int k = __shfl(tk[0], n + 16 * t);
+                if (v < bvv) {
+                    bvv = v;
+                    bkk = k;
+                    bt = t;
+                }
+            }
+            if (gq == bt) {
+#pragma unroll
+                for (int i = 0; i < 7; ++i) {
+                    tv[i] = tv[i + 1];
+                    tk[i] = tk[i + 1];
+                }
+                tv[7] = kInf;
+            }
+            const uint32_t cb = bf16_bits(bvv / g.tau), ib = bf16_bits((float)bkk / dn);
+            if (rnd & 1) {
+                fw[rnd >> 1] |= cb << 16;
+                fw[4 + (rnd >> 1)] |= ib << 16;
+            } else {
+                fw[rnd >> 1] = cb;
+                fw[4 + (rnd >> 1)] = ib;
+            }
+        }
+        if (gq == 0 && pin) {
+            const uint32_t lb = bf16_bits((float)lp[0] / 255.0f);
+            uint4* dst = reinterpret_cast<uint4*>(job.feat + ((size_t)py * g.W + px) * 32);
+            dst[0] = make_uint4(fw[0], fw[1], fw[2], fw[3]);
+            dst[1] = make_uint4(fw[4], fw[5], fw[6], fw[7]);
+            dst[2] = make_uint4(lb, 0u, 0u, 0u);
+            dst[3] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
 }
 
 __device__ __forceinline__ void load_tables(const Tables& tb, int R, unsigned char* smem, int nthreads)
@@ -539,6 +629,16 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma(TileJob job, Tables tb)
     mfma_tile<R, CH, NW>(job, blockIdx.x, blockIdx.y, smem, threadIdx.x);
 }
 
+// One workgroup per tile of one gray frame, with the surrogate's features.
+template <int R, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fbs_mfma_feat(TileJob job, Tables tb)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    load_tables(tb, R, smem, 64 * NW);
+    __syncthreads();
+    mfma_tile<R, 1, NW, true>(job, blockIdx.x, blockIdx.y, smem, threadIdx.x);
+}
+
 // Persistent workgroups over a queue of (pair, tile) items of many frames of
 // one radius / channel class.  Every workgroup pops items until the queue is
 // empty, so every wave reaches the end.
@@ -552,20 +652,27 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __r
                                                             float* const* __restrict__ subs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_item;
+    __shared__ int s_next[2];
     constexpr int kThreads = 64 * NW;
+    if (threadIdx.x == 0) s_next[0] = atomicAdd(counter, 1);
+    int buf = 0, cur_pair = -1;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-        __syncthreads();   // also: every wave is done with the previous tile's LDS
+        __syncthreads();   // s_next[buf] visible; every wave is done with the previous tile
         // uniform across the workgroup: keep the item, its pair and geometry
         // in scalar registers
-        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        const int it = __builtin_amdgcn_readfirstlane(s_next[buf]);
         if (it >= n_items) break;
+        // claim the next item now so the atomic's round trip overlaps this tile
+        if (threadIdx.x == 0) s_next[buf ^ 1] = atomicAdd(counter, 1);
+        buf ^= 1;
         const int2 w = items[it];
         const BatchPair& bp = pairs[w.x];
-        load_tables(bp.tb, R, smem, kThreads);
-        __syncthreads();   // tables visible; s_item read by every wave
-        TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr};
+        if (w.x != cur_pair) {   // items are grouped by pair: reload tables only on a change
+            load_tables(bp.tb, R, smem, kThreads);
+            cur_pair = w.x;
+            __syncthreads();
+        }
+        TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr, nullptr};
         // an opaque copy of the thread index per item keeps the compiler from
         // hoisting the tile's index arithmetic out of the loop (it would stay
         // live in registers across every item)
@@ -575,13 +682,43 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __r
     }
 }
 
-constexpr int kLdsLimit = 64 * 1024;
+// One workgroup per (pair, tile) item of one class: the same tile code as
+// the per-frame kernel, the item taken from blockIdx.
+template <int R, int CH, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fbs_mfma_items(const BatchPair* __restrict__ pairs,
+                                                            const int2* __restrict__ items,
+                                                            const uint8_t* const* __restrict__ Ls,
+                                                            const uint8_t* const* __restrict__ Rs,
+                                                            int32_t* const* __restrict__ disps,
+                                                            float* const* __restrict__ subs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 w = items[blockIdx.x];
+    const BatchPair& bp = pairs[w.x];
+    load_tables(bp.tb, R, smem, 64 * NW);
+    __syncthreads();
+    TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr, nullptr};
+    mfma_tile<R, CH, NW>(job, w.y % bp.tiles_x, w.y / bp.tiles_x, smem, threadIdx.x);
+}
+
+constexpr int kLdsLimit = 160 * 1024;  // per workgroup and per CU on gfx950
+constexpr int kMaxNb = 16;             // disparity blocks per slab
+constexpr int kMaxR12 = 7;  // largest radius built with 12-wave workgroups
+
+// deepest slab (>= 1) whose layout fits `budget` bytes
+int deepest_nb(const Geom& g, int nw, int budget)
+{
+    const int nblk = (g.D + 15) >> 4;
+    int nb = 1;
+    while (nb < nblk && nb < kMaxNb && mfma_layout(g.r, g.C, g.D, nb + 1, nw).bytes <= budget) ++nb;
+    return nb;
+}
 
 int max_nb(int r, int ch, int D, int nw)
 {
     const int nblk = (D + 15) >> 4;
     int nb = 1;
-    while (nb < nblk && nb < 4 && mfma_layout(r, ch, D, nb + 1, nw).bytes <= kLdsLimit) ++nb;
+    while (nb < nblk && nb < kMaxNb && mfma_layout(r, ch, D, nb + 1, nw).bytes <= kLdsLimit) ++nb;
     return nb;
 }
 
@@ -596,9 +733,44 @@ hipError_t launch_frame(const TileJob& job, const Tables& t, hipStream_t s)
 }
 
 template <int R, int CH, int NW>
+struct FeatOccupancy {
+    static hipError_t run(int lds, int* blocks)
+    {
+        if constexpr (CH != 1 || NW != 8) {
+            return hipErrorInvalidValue;
+        } else {
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fbs_mfma_feat<R, NW>,
+                                                                64 * NW, lds);
+        }
+    }
+};
+
+template <int R, int CH, int NW>
+struct FeatLauncher {
+    static hipError_t run(const TileJob& job, const Tables& t, hipStream_t s)
+    {
+        if constexpr (CH != 1 || NW != 8) {
+            return hipErrorInvalidValue;
+        } else {
+            const MfmaLayout lay = mfma_layout(R, 1, job.g.D, job.nb, NW);
+            if (lay.bytes > kLdsLimit) return hipErrorInvalidConfiguration;
+            dim3 grid((job.g.W + 2 * NW - 1) / (2 * NW), (job.g.H + kTileH - 1) / kTileH);
+            hipLaunchKernelGGL((k_fbs_mfma_feat<R, NW>), grid, dim3(64 * NW), lay.bytes, s, job, t);
+            return hipGetLastError();
+        }
+    }
+};
+
+template <int R, int CH, int NW>
 hipError_t launch_batch(const BatchClass& bc, hipStream_t s)
 {
     if (bc.lds <= 0 || bc.lds > kLdsLimit) return hipErrorInvalidConfiguration;
+    if (bc.one_wg_per_item) {
+        if (bc.n_items < 1) return hipSuccess;
+        hipLaunchKernelGGL((k_fbs_mfma_items<R, CH, NW>), dim3(bc.n_items), dim3(64 * NW), bc.lds,
+                           s, bc.pairs, bc.items, bc.L, bc.R, bc.disp, bc.sub);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_fbs_mfma_batch<R, CH, NW>), dim3(bc.grid), dim3(64 * NW), bc.lds, s,
                        bc.pairs, bc.items, bc.n_items, bc.counter, bc.L, bc.R, bc.disp, bc.sub);
     return hipGetLastError();
@@ -616,18 +788,32 @@ hipError_t dispatch_r(int r, A&&... a)
     case 5: return F<5, CH, NW>::run(a...);
     case 6: return F<6, CH, NW>::run(a...);
     case 7: return F<7, CH, NW>::run(a...);
-    case 8: return F<8, CH, NW>::run(a...);
-    case 9: return F<9, CH, NW>::run(a...);
-    case 10: return F<10, CH, NW>::run(a...);
-    default: return hipErrorInvalidValue;
+    default: break;
     }
+    // 12-wave workgroups cap a wave at 168 registers: above r = 7 the tile
+    // spills, so those are not built
+    if constexpr (NW != 12) {
+        switch (r) {
+        case 8: return F<8, CH, NW>::run(a...);
+        case 9: return F<9, CH, NW>::run(a...);
+        case 10: return F<10, CH, NW>::run(a...);
+        default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 template <template <int, int, int> class F, typename... A>
 hipError_t dispatch(int r, int ch, int nw, A&&... a)
 {
-    if (ch == 3) return nw == 4 ? dispatch_r<F, 3, 4>(r, a...) : dispatch_r<F, 3, 8>(r, a...);
-    return nw == 4 ? dispatch_r<F, 1, 4>(r, a...) : dispatch_r<F, 1, 8>(r, a...);
+    if (ch == 3) {
+        if (nw == 4) return dispatch_r<F, 3, 4>(r, a...);
+        if (nw == 12) return dispatch_r<F, 3, 12>(r, a...);
+        return dispatch_r<F, 3, 8>(r, a...);
+    }
+    if (nw == 4) return dispatch_r<F, 1, 4>(r, a...);
+    if (nw == 12) return dispatch_r<F, 1, 12>(r, a...);
+    return dispatch_r<F, 1, 8>(r, a...);
 }
 
 template <int R, int CH, int NW>
@@ -641,6 +827,15 @@ struct FrameLauncher {
 template <int R, int CH, int NW>
 struct BatchLauncher {
     static hipError_t run(const BatchClass& bc, hipStream_t s) { return launch_batch<R, CH, NW>(bc, s); }
+};
+
+template <int R, int CH, int NW>
+struct FrameOccupancy {
+    static hipError_t run(int lds, int* blocks)
+    {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fbs_mfma<R, CH, NW>, 64 * NW,
+                                                            lds);
+    }
 };
 
 template <int R, int CH, int NW>
@@ -692,17 +887,77 @@ hipError_t launch_mfma_cfg(const Geom& g, const Tables& t, const MfmaCfg& cfg, c
 {
     float scap;
     if (!mfma_supported(g) || !scaled_cap(g, &scap)) return hipErrorInvalidValue;
-    if ((cfg.nw != 4 && cfg.nw != 8) || cfg.nb < 1 || cfg.nb > max_nb(g.r, g.C, g.D, cfg.nw))
+    if (!mfma_nw_valid(g, cfg.nw) || cfg.nb < 1 || cfg.nb > max_nb(g.r, g.C, g.D, cfg.nw))
         return hipErrorInvalidValue;
-    const TileJob job{g, scap, cfg.nb, L, R, disp, sub, agg};
+    const TileJob job{g, scap, cfg.nb, L, R, disp, sub, agg, nullptr};
     return dispatch<FrameLauncher>(g.r, g.C, cfg.nw, job, t, s);
+}
+
+bool mfma_nw_valid(const Geom& g, int nw)
+{
+    return (nw == 4 || nw == 8 || (nw == 12 && g.r <= kMaxR12)) &&
+           mfma_layout(g.r, g.C, g.D, 1, nw).bytes <= kLdsLimit;
+}
+
+// Default configuration: the waves per workgroup that keep the most waves
+// resident per CU (registers decide; LDS is then budgeted so that it does not
+// lower that count), with the deepest slab that fits the budget; ties go to 8
+// waves.  Cached per (radius, channels, disparity blocks) once the device has
+// answered.
+MfmaCfg mfma_default_cfg(const Geom& g)
+{
+    static std::atomic<int> cache[kMaxR + 1][2][FBS_MAX_DISP / 16 + 1];
+    const int nblk = (g.D + 15) >> 4;
+    std::atomic<int>& slot = cache[g.r][g.C == 3][nblk];
+    int packed = slot.load(std::memory_order_relaxed);
+    if (packed == 0) {
+        int best = -1;
+        for (int cand : {8, 12, 4}) {
+            if (!mfma_nw_valid(g, cand)) continue;
+            int blocks = 0;
+            const int lds1 = mfma_layout(g.r, g.C, g.D, 1, cand).bytes;
+            if (dispatch<FrameOccupancy>(g.r, g.C, cand, lds1, &blocks) != hipSuccess || blocks < 1)
+                continue;
+            const int nb = deepest_nb(g, cand, kLdsLimit / blocks);
+            if (blocks * cand > best) {
+                best = blocks * cand;
+                packed = (cand << 8) | nb;
+            }
+        }
+        if (best > 0) slot.store(packed, std::memory_order_relaxed);
+        else packed = (8 << 8) | max_nb(g.r, g.C, g.D, 8);
+    }
+    return MfmaCfg{packed >> 8, packed & 255};
+}
+
+hipError_t launch_mfma_features(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
+                                float* sub, uint16_t* feat, hipStream_t s)
+{
+    float scap;
+    if (g.C != 1 || g.D < 8 || !mfma_supported(g) || !scaled_cap(g, &scap) || !feat)
+        return hipErrorInvalidValue;
+    // slab depth: the deepest whose LDS keeps the register-limited number of
+    // workgroups per CU resident (cached per radius and disparity blocks)
+    static std::atomic<int> cache[kMaxR + 1][FBS_MAX_DISP / 16 + 1];
+    const int nblk = (g.D + 15) >> 4;
+    int nb = cache[g.r][nblk].load(std::memory_order_relaxed);
+    if (nb == 0) {
+        int blocks = 0;
+        if (dispatch_r<FeatOccupancy, 1, 8>(g.r, mfma_layout(g.r, 1, g.D, 1, 8).bytes, &blocks) !=
+                hipSuccess ||
+            blocks < 1)
+            blocks = 1;
+        nb = deepest_nb(g, 8, kLdsLimit / blocks);
+        cache[g.r][nblk].store(nb, std::memory_order_relaxed);
+    }
+    const TileJob job{g, scap, nb, L, R, nullptr, sub, nullptr, feat};
+    return dispatch_r<FeatLauncher, 1, 8>(g.r, job, t, s);
 }
 
 hipError_t launch_mfma(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
                        int32_t* disp, float* sub, float* agg, hipStream_t s)
 {
-    const MfmaCfg cfg{8, max_nb(g.r, g.C, g.D, 8)};
-    return launch_mfma_cfg(g, t, cfg, L, R, disp, sub, agg, s);
+    return launch_mfma_cfg(g, t, mfma_default_cfg(g), L, R, disp, sub, agg, s);
 }
 
 hipError_t launch_mfma_batch(const BatchClass& bc, hipStream_t s)

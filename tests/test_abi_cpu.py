@@ -119,3 +119,16 @@ def test_status_strings_and_version():
     assert L.fbs_status_str(0) == "ok"
     assert L.fbs_status_str(L.FBS_E_HIP) == "HIP error"
     assert re.match(r"\d+\.\d+\.\d+", L.fbs_version())
+
+
+def test_header_constants_match_binding():
+    """Every #define and enum value of include/fbs.h has the same value in the binding."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "fbs.h")).read()
+    found = dict(re.findall(r"#define\s+(FBS_\w+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", hdr))
+    found.update(re.findall(r"\b(FBS_\w+)\s*=\s*(-?\d+)", hdr))
+    assert len(found) >= 12
+    for name, val in found.items():
+        assert hasattr(L, name), name
+        assert getattr(L, name) == int(val, 0), name

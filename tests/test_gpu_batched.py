@@ -77,6 +77,23 @@ def test_plan_equals_per_pair_run_bitwise():
     plan.close()
 
 
+def test_per_tile_plan_equals_per_pair_run_bitwise():
+    """FBS_PLAN_PER_TILE: one workgroup per (pair, tile) item, same bits."""
+    pairs = _batch()
+    params = [fbs.params_for(wl) for wl, _ in pairs]
+    plan = L.FbsPlan(params, per_tile=True)
+    assert plan.num_launches() == 2
+    Ls, Rs, Ds, Ss = _run_plan(plan, pairs)
+    _run_plan(plan, pairs)                      # replay with fresh buffers
+    Ls, Rs, Ds, Ss = _run_plan(plan, pairs)
+    for i, (wl, _) in enumerate(pairs):
+        d, s = fbs.run(params[i], Ls[i], Rs[i])
+        np.testing.assert_array_equal(Ds[i], d.cpu().numpy(), err_msg=wl.name)
+        np.testing.assert_array_equal(Ss[i].view(np.uint32), s.cpu().numpy().view(np.uint32),
+                                      err_msg=wl.name)
+    plan.close()
+
+
 def test_plan_tuning_cache_roundtrip(tmp_path):
     pairs = _batch()[:3]
     params = [fbs.params_for(wl) for wl, _ in pairs]
@@ -88,7 +105,7 @@ def test_plan_tuning_cache_roundtrip(tmp_path):
     data = json.load(open(cache))
     assert data["arch"] == "gfx950" and len(data["entries"]) == 3
     for key, (nw, nb, us) in data["entries"].items():
-        assert nw in (4, 8) and nb >= 1 and us > 0
+        assert nw in (4, 8, 12) and nb >= 1 and us > 0
     # a plan built from the cache alone picks the same configurations
     plan2 = L.FbsPlan(params, tune_cache=cache, tune=False)
     assert [plan2.pair_config(i) for i in range(3)] == tuned
@@ -129,7 +146,7 @@ def _max_nb(params, wl, tmp_path, nw):
     """Deepest slab the library accepts for one pair at `nw` waves (probed
     through single-pair plans built from a cache entry)."""
     best = 0
-    for nb in (1, 2, 3, 4):
+    for nb in range(1, 17):
         cache = tmp_path / f"probe_{wl.name}_{nb}.json"
         key = f"{wl.width},{wl.height},1,{wl.n_disp},{wl.radius}"
         cache.write_text(json.dumps({"arch": "gfx950", "entries": {key: [nw, nb, 1.0]}}))
@@ -141,30 +158,32 @@ def _max_nb(params, wl, tmp_path, nw):
 
 
 def test_plan_class_mixing_slab_depths(tmp_path):
-    """One class (r = 10, 4 waves) holding a 32-disparity pair at its deepest
-    slab and a 96-disparity pair at depth 1: the launch must size LDS for the
-    largest per-pair layout, not for (largest D) x (deepest slab)."""
-    specs = [(80, 40, 0, 31), (120, 40, 0, 95), (130, 33, 2, 97)]
+    """One class (r = 10, 8 waves) holding a 64-disparity pair at its deepest
+    slab and two 256-disparity pairs at theirs (shallower): the launch must
+    size LDS for the largest per-pair layout, not for (largest D) x (deepest
+    slab), and every pair keeps fbs_run's bits."""
+    specs = [(80, 40, 0, 63), (300, 40, 0, 255), (310, 33, 2, 257)]
     pairs = []
     for i, (W, H, d0, d1) in enumerate(specs):
         wl = scenes.Workload(f"m{i}", W, H, 1, d0, d1, 10, 10.0, 10.0, 40.0,
                              scene="slanted", seed=700 + i, n_planes=3)
         pairs.append((wl, scenes.make_pair(wl)))
     params = [fbs.params_for(wl) for wl, _ in pairs]
-    nbs = [_max_nb(p, wl, tmp_path, 4) for p, (wl, _) in zip(params, pairs)]
-    _say("deepest slabs at 4 waves", nbs)
+    nbs = [_max_nb(p, wl, tmp_path, 8) for p, (wl, _) in zip(params, pairs)]
+    _say("deepest slabs at 8 waves", nbs)
     assert nbs[0] > nbs[1] >= 1 and nbs[2] >= 1
     cache = tmp_path / "tune.json"
-    entries = {f"{wl.width},{wl.height},1,{wl.n_disp},10": [4, nb, 1.0]
+    entries = {f"{wl.width},{wl.height},1,{wl.n_disp},10": [8, nb, 1.0]
                for (wl, _), nb in zip(pairs, nbs)}
     cache.write_text(json.dumps({"arch": "gfx950", "entries": entries}))
-    plan = L.FbsPlan(params, tune_cache=str(cache), tune=False)
-    cfgs = [plan.pair_config(i) for i in range(len(pairs))]
-    _say("configs", cfgs)
-    assert cfgs == [(1, 4, nb) for nb in nbs]
-    Ls, Rs, Ds, Ss = _run_plan(plan, pairs)
-    for i, (wl, _) in enumerate(pairs):
-        d, s = fbs.run(params[i], Ls[i], Rs[i])
-        np.testing.assert_array_equal(Ds[i], d.cpu().numpy(), err_msg=wl.name)
-        np.testing.assert_array_equal(Ss[i].view(np.uint32), s.cpu().numpy().view(np.uint32))
-    plan.close()
+    for per_tile in (False, True):
+        plan = L.FbsPlan(params, tune_cache=str(cache), tune=False, per_tile=per_tile)
+        cfgs = [plan.pair_config(i) for i in range(len(pairs))]
+        _say("configs", cfgs)
+        assert cfgs == [(1, 8, nb) for nb in nbs]
+        Ls, Rs, Ds, Ss = _run_plan(plan, pairs)
+        for i, (wl, _) in enumerate(pairs):
+            d, s = fbs.run(params[i], Ls[i], Rs[i])
+            np.testing.assert_array_equal(Ds[i], d.cpu().numpy(), err_msg=wl.name)
+            np.testing.assert_array_equal(Ss[i].view(np.uint32), s.cpu().numpy().view(np.uint32))
+        plan.close()

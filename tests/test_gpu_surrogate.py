@@ -109,6 +109,30 @@ def test_features_bit_exact(W, H, D, tau):
     sur.close()
 
 
+@pytest.mark.parametrize("W,H,D,r,flags", [(96, 64, 24, 3, 0), (130, 37, 40, 3, 0),
+                                           (200, 60, 96, 5, 0), (70, 30, 9, 2, 0),
+                                           (96, 64, 24, 3, L.FBS_F_FORCE_VALU)])
+def test_cheap_run_equals_run_plus_features(W, H, D, r, flags):
+    """fbs_surrogate_cheap_run (one launch on the matrix cores) = fbs_run's
+    subpixel map and fbs_surrogate_features of its agg_out, bit for bit."""
+    wl = scenes.Workload("cr", W, H, 1, 2, 2 + D - 1, r, float(r), 10.0, 40.0, scene="slanted",
+                         seed=W + D, n_planes=4)
+    pr = scenes.make_pair(wl)
+    p = fbs.params_for(wl, flags=flags)
+    Lt, Rt = torch.from_numpy(pr.left).to(DEV), torch.from_numpy(pr.right).to(DEV)
+    sur = L.FbsSurrogate(W, H, D)
+    sub = torch.full((H, W), -1.0, dtype=torch.float32, device=DEV)
+    feat = torch.full((H, W, 32), -1, dtype=torch.int16, device=DEV)
+    sur.cheap_run(p, Lt, Rt, sub, feat)
+    _, sub2, agg = fbs.run(p, Lt, Rt, want_agg=True)
+    feat2 = torch.empty_like(feat)
+    sur.features(p, Lt, agg, feat2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(sub.cpu().numpy().view(np.uint32), sub2.cpu().numpy().view(np.uint32))
+    np.testing.assert_array_equal(feat.cpu().numpy(), feat2.cpu().numpy())
+    sur.close()
+
+
 def test_features_reject_rgb_and_small_range():
     sur = L.FbsSurrogate(32, 8, 16)
     feat = torch.empty((8, 32, 32), dtype=torch.int16, device=DEV)
