@@ -20,6 +20,21 @@ __device__ __forceinline__ float ncc_cost(int n, int sl, int sll, int sr, int sr
     return (float)(1.0 - c);
 }
 
+// Eq. 10: d^s = d + (c(d-1) - c(d+1)) / (2c(d-1) + 2c(d+1) - 4c(d)); d itself
+// at the ends of the range or where the denominator is not positive.  Every
+// operation rounds in the order written (no contraction into fused
+// multiply-adds), so all kernels produce the same bits from the same costs.
+__device__ __forceinline__ float eq10_subpixel(int d, bool interior, float cm, float c0, float cp)
+{
+#pragma clang fp contract(off)
+    float ds = (float)d;
+    if (interior) {
+        const float den = 2.0f * cm + 2.0f * cp - 4.0f * c0;
+        if (den > 0.0f) ds += (cm - cp) / den;
+    }
+    return ds;
+}
+
 // Running winner-take-all over ascending disparities (Section II-C, ties to
 // the lowest d) that also keeps the two neighbours of the current best for
 // the parabola of Eq. 10.
@@ -47,16 +62,10 @@ struct Wta {
         }
         prev = v;
     }
-    // Eq. 10: d^s = d + (c(d-1) - c(d+1)) / (2c(d-1) + 2c(d+1) - 4c(d))
     __device__ __forceinline__ void finish(int dmin, int D, int32_t* disp, float* sub) const
     {
-        float ds = (float)(dmin + bi);
-        if (bi > 0 && bi < D - 1) {
-            const float den = 2.0f * cm + 2.0f * cp - 4.0f * best;
-            if (den > 0.0f) ds += (cm - cp) / den;
-        }
         *disp = dmin + bi;
-        *sub = ds;
+        *sub = eq10_subpixel(dmin + bi, bi > 0 && bi < D - 1, cm, best, cp);
     }
 };
 

@@ -90,6 +90,7 @@ struct BatchClass {
     int lds;  // dynamic LDS bytes: the largest layout of any pair in the class
     int grid;             // persistent workgroups
     int one_wg_per_item;  // 1: one workgroup per item instead of persistent ones
+    int co;               // 1: every pair's slab holds all its disparity blocks
     const BatchPair* pairs;
     const int2* items;
     int n_items;
@@ -100,6 +101,7 @@ struct BatchClass {
     float* const* sub;
 };
 hipError_t launch_mfma_batch(const BatchClass& bc, hipStream_t s);
-int mfma_batch_blocks_per_cu(int r, int ch, int nw, int lds_bytes);
+int mfma_batch_blocks_per_cu(int r, int ch, int nw, int lds_bytes, bool co);
+bool mfma_use_co(int D, int nb);  // chunk-outer kernels: one slab holds every block
 
 }  // namespace fbs

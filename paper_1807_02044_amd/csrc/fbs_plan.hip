@@ -245,16 +245,17 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
     if (cache_dirty) write_cache(tune_cache_path, cache);
 
     // classes and their work lists (most expensive pairs first)
-    std::map<int, std::vector<int>> by_class;  // key r*100 + ch*10 + nw/4
+    std::map<int, std::vector<int>> by_class;  // key r*1000 + ch*100 + nw/4*10 + co
     for (int i = 0; i < n; ++i)
         if (p->mfma[i]) {
             const Geom g = api_geom(&params[i]);
-            by_class[g.r * 100 + g.C * 10 + p->cfg[i].nw / 4].push_back(i);
+            const int co = mfma_use_co(g.D, p->cfg[i].nb) ? 1 : 0;
+            by_class[g.r * 1000 + g.C * 100 + p->cfg[i].nw / 4 * 10 + co].push_back(i);
         }
     std::vector<BatchPair> pairs(n);
     std::vector<int2> items;
     struct Span {
-        int r, ch, nw, first, count, lds;
+        int r, ch, nw, co, first, count, lds;
     };
     std::vector<Span> spans;
     for (auto& kv : by_class) {
@@ -263,7 +264,8 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
             const Geom ga = api_geom(&params[a]), gb = api_geom(&params[b]);
             return ga.D > gb.D;  // cost per tile grows with D
         });
-        Span sp{kv.first / 100, (kv.first / 10) % 10, (kv.first % 10) * 4, (int)items.size(), 0, 0};
+        Span sp{kv.first / 1000, (kv.first / 100) % 10, ((kv.first / 10) % 10) * 4, kv.first % 10,
+                (int)items.size(), 0, 0};
         for (int i : ids) {
             const Geom g = api_geom(&params[i]);
             const int tw = 2 * p->cfg[i].nw;
@@ -311,7 +313,8 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
         bc.ch = sp.ch;
         bc.nw = sp.nw;
         bc.lds = sp.lds;
-        const int per_cu = mfma_batch_blocks_per_cu(sp.r, sp.ch, sp.nw, sp.lds);
+        bc.co = sp.co;
+        const int per_cu = mfma_batch_blocks_per_cu(sp.r, sp.ch, sp.nw, sp.lds, sp.co != 0);
         bc.grid = std::max(1, std::min(sp.count, cus * per_cu));
         bc.one_wg_per_item = (flags & FBS_PLAN_PER_TILE) ? 1 : 0;
         bc.pairs = p->d_pairs;

@@ -1,0 +1,1013 @@
+// mfma_tile.h - fused TAD path with Eq. 6 on the matrix cores (gfx950): the
+// tile code, its kernels and their launch helpers, shared by the per-frame,
+// batched and surrogate-feature translation units.
+//
+// For a group of 16 pixels (a 2x8 or 4x4 block) let Q be the union of their
+// (2r+1)^2 windows.  Eq. 6's numerator for the group is a dense contraction
+//     num(d, p) = sum_{q in Q} C(q, d) * W(p, q),   W(p, q) = 0 outside p's window,
+// so each 16-disparity x 16-pixel block is a chain of v_mfma_f32_16x16x32_f16
+// over K = |Q| padded to a multiple of 32:
+//   * A operand (16 x 32): costs.  TAD costs are small integers (gray
+//     min(|dI|, tau); RGB 3*min(mean |dI|, tau) = min(sum |dI|, 3 tau)), exact
+//     in fp16 whenever the cap is (checked on the host).
+//   * B operand (32 x 16): support weights of Eqs. 7-8, computed once per
+//     (pixel, window position), scaled by 2^14 and split into fp16 hi + lo
+//     (|w - hi - lo| <= 2^-22 w); both halves stay in registers for the whole
+//     disparity range, so each weight is formed once and used for every d.
+//   * C/D (16 x 16): fp32 accumulators, one chain for hi and one for lo.
+// The denominator of Eq. 6 does not depend on d, so the WTA and Eq. 10 run on
+// the numerators directly (Eq. 10 is invariant under positive scaling); it is
+// only formed when the aggregated volume is requested.
+//
+// Workgroup: 8 waves, one 16-pixel group per wave, covering an 8x16 pixel
+// tile.  The left tile and the right strip it can match are staged in LDS as
+// bytes once.  The disparity axis is walked in slabs of nb 16-disparity
+// blocks: per slab all waves build the fp16 cost planes of the tile's window
+// union in LDS (each cost computed once per workgroup), then every wave runs
+// its MFMA chains.  Lane group g (lanes 16g..16g+15) of the 16x16 result holds
+// disparities g*Q + 4b + j (Q = padded D / 4) of pixel lane%16, so each lane
+// sees one contiguous quarter of the disparity range in ascending order and
+// keeps a running first-minimum WTA with the Eq. 10 neighbours; the four
+// quarters are merged with lane shuffles at the end.
+#pragma once
+
+#include <algorithm>
+#include <atomic>
+
+#include "fbs_device.h"
+#include "fbs_internal.h"
+
+namespace fbs {
+
+namespace {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTileH = 8;         // tile rows; a tile is kTileH x (2 * waves) pixels
+constexpr float kWScale = 16384.0f;  // 2^14: keeps small weights in fp16's normal range
+constexpr int kMaxR = 10;
+constexpr int kCoMax = 6;  // chunk-outer path: at most this many 16-disparity blocks
+// range factor by signed intensity difference -255..255 (no abs per weight),
+// padded to a multiple of 4 floats
+constexpr int kLutN = 512;
+
+constexpr int n_chunks(int gh, int gw, int r) { return (((gh + 2 * r) * ((gw + 2 * r + 7) / 8)) + 3) / 4; }
+
+// Geometry of one radius: group shape (the one with fewer K chunks), octets,
+// chunks, and the LDS tile of a kTileH x tile_w workgroup tile.
+struct Cfg {
+    int GH, GW;  // group shape
+    int OPR;     // 8-wide octets per union row
+    int NOCT;    // octets of the group's union
+    int NCH;     // K chunks of 32
+    int GX, GY;  // groups across / down the tile
+    int LH, LW;  // rows / padded columns of the tile's union
+    // cost plane stride in halves: PS/2 = 4 (mod 64) dwords, so the 16 lanes
+    // reading 16 planes at one offset hit 16 distinct 4-bank groups
+    int PS;
+};
+
+__host__ __device__ constexpr Cfg cfg_of(int r, int tile_w)
+{
+    const bool wide = n_chunks(2, 8, r) <= n_chunks(4, 4, r);
+    Cfg c{};
+    c.GH = wide ? 2 : 4;
+    c.GW = wide ? 8 : 4;
+    c.OPR = (c.GW + 2 * r + 7) / 8;
+    c.NOCT = (c.GH + 2 * r) * c.OPR;
+    c.NCH = (c.NOCT + 3) / 4;
+    c.GX = tile_w / c.GW;
+    c.GY = kTileH / c.GH;
+    c.LH = kTileH + 2 * r;
+    c.LW = ((c.GX - 1) * c.GW + 8 * c.OPR + 7) / 8 * 8;
+    c.PS = ((c.LH * c.LW + 127) / 128) * 128 + 8;
+    return c;
+}
+
+__host__ __device__ constexpr int align16(int b) { return (b + 15) & ~15; }
+
+struct MfmaLayout {
+    int lwb, rwb;     // bytes per left-tile / right-strip row (channels interleaved)
+    int off_wx, off_wy, off_L, off_R, off_cost;
+    int bytes;
+};
+
+__host__ __device__ constexpr MfmaLayout mfma_layout(int r, int ch, int D, int nb, int nw)
+{
+    const int tile_w = 2 * nw;
+    const Cfg c = cfg_of(r, tile_w);
+    MfmaLayout m{};
+    m.lwb = ch * c.LW;
+    // +16: slack for the unaligned reads of the last octet of a row
+    m.rwb = (ch * (c.LW + D - 1) + 16 + 3) & ~3;
+    m.off_wx = (kLutN + 32) * 4;  // after the signed range LUT and the spatial factors
+    m.off_wy = m.off_wx + tile_w * c.LW * 4;
+    m.off_L = m.off_wy + align16(kTileH * c.LH * 4);
+    m.off_R = m.off_L + align16(c.LH * m.lwb);
+    m.off_cost = m.off_R + align16(c.LH * m.rwb);
+    m.bytes = m.off_cost + 16 * nb * c.PS * 2;
+    return m;
+}
+
+template <bool kAligned16>
+__device__ __forceinline__ h8 lds_h8(const _Float16* p)
+{
+    if (kAligned16) return *reinterpret_cast<const h8*>(p);
+    const h4 a = *reinterpret_cast<const h4*>(p);
+    const h4 b = *reinterpret_cast<const h4*>(p + 4);
+    return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+// v_perm_b32 picks bytes of the 64-bit {hi, lo} (selector 0-3: lo, 4-7: hi,
+// 0x0c: zero).  With hi = 0x64646464, bytes b0, b1 of lo become the fp16 pair
+// (1024 + b0, 1024 + b1): the byte fills the mantissa under the exponent of
+// 1024, so differences of such pairs are exact.
+__device__ __forceinline__ h2 bytes01_f16(uint32_t v)
+{
+    return __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, v, 0x04010400u));
+}
+__device__ __forceinline__ h2 bytes23_f16(uint32_t v)
+{
+    return __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, v, 0x04030402u));
+}
+
+// Dwords w[0..N-1] of an LDS byte array starting at an arbitrary byte offset:
+// N+1 aligned dword reads (the row slack of the strip keeps the last in bounds).
+template <int N>
+__device__ __forceinline__ void load_unaligned(const uint8_t* base, int off, uint32_t (&w)[N])
+{
+    const uint32_t* a = reinterpret_cast<const uint32_t*>(base) + (off >> 2);
+    const uint32_t sh = (uint32_t)(off & 3);
+    uint32_t t[N + 1];
+#pragma unroll
+    for (int i = 0; i <= N; ++i) t[i] = a[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] = __builtin_amdgcn_alignbyte(t[i + 1], t[i], sh);
+}
+
+// Pixel j (bytes 3j..3j+2, zero-extended) of 8 interleaved RGB pixels.
+__device__ __forceinline__ uint32_t rgb_pixel(const uint32_t (&a)[6], int j)
+{
+    const int b = 3 * j, i = b >> 2, s = b & 3;
+    const uint32_t hi = a[i + 1 < 6 ? i + 1 : 5];
+    return __builtin_amdgcn_perm(hi, a[i], 0x0c000000u | ((s + 2) << 16) | ((s + 1) << 8) | s);
+}
+
+// fp16 pair (s0, s1) of two integers below 1024
+__device__ __forceinline__ h2 small_int_pair(uint32_t s0, uint32_t s1)
+{
+    const h2 off = {(_Float16)1024.0f, (_Float16)1024.0f};
+    return __builtin_bit_cast(h2, (s0 | (s1 << 16)) | 0x64006400u) - off;
+}
+
+// One tile's worth of work, shared by the per-frame and the batched kernels.
+struct TileJob {
+    Geom g;
+    float scap;  // cap as the kernel sees it (tau, or 3 tau for RGB)
+    int nb;      // 16-disparity blocks per LDS slab
+    const uint8_t* L;
+    const uint8_t* R;
+    int32_t* disp;
+    float* sub;
+    float* agg;
+    uint16_t* feat;  // FEAT tiles only: learned-surrogate features [H][W][32] BF16
+};
+
+// The caller has put the range LUT by signed difference (kLutN floats, entry
+// 255 + dI) at smem[0] and the spatial factors exp(-k^2/gd^2), k = 0..31 (0
+// beyond the radius), right after it, and synchronised the workgroup.
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// FEAT: besides the maps, write the learned surrogate's input features of
+// each pixel: the 8 lowest aggregated costs (ascending, ties to the lower d)
+// over the cost cap, their indices (d - d_min) / (D - 1), and the left
+// intensity / 255, as BF16 in 32 channels (the rest zero).  The aggregated
+// cost is formed exactly as for agg_out, so the features equal those of
+// fbs_surrogate_features applied to agg_out bit for bit.
+//
+// CO (chunk-outer): the whole disparity range sits in one LDS slab (nb equal to
+// the number of 16-disparity blocks, at most kCoMax); each K chunk's weights
+// are formed and immediately applied to every block, so only one chunk of
+// weights is live and the weight arithmetic of one chunk overlaps the matrix
+// work of the previous.  Otherwise the weights of every chunk are formed once,
+// held in registers, and applied slab by slab.  Both accumulate each block the
+// same way - hi and lo products in two chains over the chunks in order, summed
+// at the end - so the results do not depend on the path, the slab depth or
+// the waves per workgroup.
+template <int R, int CH, int NW, bool FEAT = false, bool CO = false>
+__device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int tile_y,
+                                          unsigned char* smem, int tid)
+{
+    // Every floating-point operation here rounds as written: a fused
+    // multiply-add in place of w - hi (w a product) would change lo, and the
+    // compiler's choice could differ between kernels that share this code.
+#pragma clang fp contract(off)
+    constexpr int kThreads = 64 * NW, kTileW = 2 * NW;
+    const Geom& g = job.g;
+    const int nb = job.nb;
+    const float scap = job.scap;
+    const uint8_t* __restrict__ Lg = job.L;
+    const uint8_t* __restrict__ Rg = job.R;
+    int32_t* __restrict__ disp = job.disp;
+    float* __restrict__ sub = job.sub;
+    float* __restrict__ agg = job.agg;
+    constexpr Cfg C = cfg_of(R, kTileW);
+    constexpr int GH = C.GH, GW = C.GW, OPR = C.OPR, NOCT = C.NOCT, NCH = C.NCH;
+    constexpr int LH = C.LH, LW = C.LW, PS = C.PS;
+    constexpr int LWB = CH * LW;
+    static_assert(C.GX * C.GY == NW, "one group per wave");
+
+    const int D = g.D;
+    const int nblk = (D + 15) >> 4;   // 16-disparity blocks
+    const int Q = nblk * 4;           // disparities per lane group
+    const MfmaLayout lay = mfma_layout(R, CH, D, nb, NW);
+    const int RWB = lay.rwb;
+    const float* s_gr = reinterpret_cast<const float*>(smem) + 255;  // index by I_q - I_p
+    const float* s_gs = s_gr - 255 + kLutN;
+    float* s_wx = reinterpret_cast<float*>(smem + lay.off_wx);
+    float* s_wy = reinterpret_cast<float*>(smem + lay.off_wy);
+    uint8_t* s_L = smem + lay.off_L;
+    uint8_t* s_R = smem + lay.off_R;
+    _Float16* s_cost = reinterpret_cast<_Float16*>(smem + lay.off_cost);
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int X0 = tile_x * kTileW, Y0 = tile_y * kTileH;
+    const int ox = X0 - R, oy = Y0 - R;           // image position of LDS tile (0,0)
+    const int dmax = g.dmin + D - 1;
+    const int rox = ox - dmax;                    // image x of right-strip column 0
+
+    // ---- stage: range LUT; spatial factor tables; left tile, right strip ----
+    // s_wx[pc][U] = exp(-(U-R-pc)^2/gd^2) for union column U of pixel column pc,
+    // 0 outside the window or the image; s_wy[pr][V] likewise along y, times
+    // the 2^14 weight scale.  Image rows are copied as bytes with channels
+    // interleaved; bytes off the image are staged as 0.
+    for (int i = tid; i < kTileW * LW; i += kThreads) {
+        const int pc = i / LW, u = i - pc * LW;
+        const int dx = abs(u - R - pc), x = ox + u;
+        s_wx[i] = (dx <= R && x >= 0 && x < g.W) ? s_gs[dx] : 0.0f;
+    }
+    for (int i = tid; i < kTileH * LH; i += kThreads) {
+        const int pr = i / LH, v = i - pr * LH;
+        const int dy = abs(v - R - pr), y = oy + v;
+        s_wy[i] = (dy <= R && y >= 0 && y < g.H) ? s_gs[dy] * kWScale : 0.0f;
+    }
+    {
+        // Bytes off the image are never weighted (their window positions have
+        // zero weight, and right pixels left of the image are replaced by the
+        // cap), so they only need to be finite: read them from clamped
+        // in-bounds addresses instead of branching.  4 bytes per thread and
+        // iteration, all loads issued before the LDS writes.
+        const int rowbytes = g.W * CH;
+        auto stage = [&](uint8_t* dst, int wb, int xb0, const uint8_t* src) {
+            const int n4 = LH * wb / 4;
+#pragma unroll 2
+            for (int i = tid; i < n4; i += kThreads) {
+                const int row = (4 * i) / wb, cb = 4 * i - row * wb;
+                const size_t rbase = (size_t)min(max(oy + row, 0), g.H - 1) * g.stride;
+                uint32_t v = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int xb = min(max(xb0 + cb + e, 0), rowbytes - 1);
+                    v |= (uint32_t)src[rbase + xb] << (8 * e);
+                }
+                reinterpret_cast<uint32_t*>(dst)[i] = v;
+            }
+        };
+        stage(s_L, LWB, ox * CH, Lg);
+        stage(s_R, RWB, rox * CH, Rg);
+    }
+    __syncthreads();
+
+    // ---- this wave's group and this lane's pixel / octet group ----
+    const int gcol0 = (wave % C.GX) * GW, grow0 = (wave / C.GX) * GH;  // in the tile
+    const int n = lane & 15, gq = lane >> 4;
+    const int prow = grow0 + n / GW, pcol = gcol0 + n % GW;               // pixel in the tile
+    const int px = X0 + pcol, py = Y0 + prow;
+    const bool pin = px < g.W && py < g.H;
+
+    // ---- support weights (Eqs. 7-8) for this lane's pixel, hi/lo fp16 ----
+    // w = wx(dx) * wy(dy) * prod_ch gr(|dI_ch|) * 2^14, then w = hi + lo
+    uint32_t lp[CH];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(prow + R) * LWB + (pcol + R) * CH + ch];
+    auto chunk_weights = [&](int c, h8& whc, h8& wlc) {
+#pragma clang fp contract(off)
+        const int o = min(4 * c + gq, NOCT - 1);  // octets past the union: weight 0
+        const bool real = 4 * c + gq < NOCT;
+        const int V = grow0 + o / OPR;                          // tile union row
+        const int U = gcol0 + (o % OPR) * 8;                    // tile union column
+        const float wy = real ? s_wy[prow * LH + V] : 0.0f;
+        const float4 wx0 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U);
+        const float4 wx1 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U + 4);
+        const float wx[8] = {wx0.x, wx0.y, wx0.z, wx0.w, wx1.x, wx1.y, wx1.z, wx1.w};
+        // 8 pixels x CH channels of the left image, as dwords (U*CH is a multiple of 4)
+        uint32_t lq[2 * CH];
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(s_L + V * LWB + U * CH);
+#pragma unroll
+        for (int i = 0; i < 2 * CH; ++i) lq[i] = q[i];
+        float wa[8], wb[8];  // w = wa * wb
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float wr = 1.0f;
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch) {
+                const int b = CH * j + ch;
+                const int iv = (int)((lq[b >> 2] >> (8 * (b & 3))) & 0xffu);
+                const float f = s_gr[iv - (int)lp[ch]];
+                wr = ch == 0 ? f : wr * f;
+            }
+            wa[j] = wx[j] * wy;
+            wb[j] = wr;
+        }
+        h8 hv, lv;
+#pragma unroll
+        for (int j2 = 0; j2 < 4; ++j2) {
+            // hi = w rounded to fp16, lo = the exact product's remainder
+            // rounded to fp16 (an explicit fused multiply-add, so every kernel
+            // forms the same bits)
+            const int j0 = 2 * j2, j1 = j0 + 1;
+            const f2 pw = {wa[j0] * wb[j0], wa[j1] * wb[j1]};
+            const h2 hi = __builtin_convertvector(pw, h2);
+            const f2 hf = __builtin_convertvector(hi, f2);
+            const f2 rem = {__builtin_fmaf(wa[j0], wb[j0], -hf[0]), __builtin_fmaf(wa[j1], wb[j1], -hf[1])};
+            const h2 lo = __builtin_convertvector(rem, h2);
+            hv[2 * j2] = hi[0];
+            hv[2 * j2 + 1] = hi[1];
+            lv[2 * j2] = lo[0];
+            lv[2 * j2 + 1] = lo[1];
+        }
+        if constexpr (!CO) {
+            // Pin the packed chunk here.  Otherwise the conversions sink towards
+            // their MFMA uses and all float weights of the tile stay live at once.
+            // (The chunk-outer path uses each chunk at once and must stay free
+            // to interleave it with the previous chunk's matrix work.)
+            uint4 hu = __builtin_bit_cast(uint4, hv), lu = __builtin_bit_cast(uint4, lv);
+            asm volatile("" : "+v"(hu.x), "+v"(hu.y), "+v"(hu.z), "+v"(hu.w), "+v"(lu.x),
+                         "+v"(lu.y), "+v"(lu.z), "+v"(lu.w));
+            whc = __builtin_bit_cast(h8, hu);
+            wlc = __builtin_bit_cast(h8, lu);
+        } else {
+            whc = hv;
+            wlc = lv;
+        }
+    };
+    h8 whi[CO ? 1 : NCH], wlo[CO ? 1 : NCH];
+    if constexpr (!CO) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) chunk_weights(c, whi[c], wlo[c]);
+    }
+    // Eq. 6's denominator (only for agg_out and features): an all-ones A
+    // operand sums each weight column, giving sum_q (hi + lo)(p, q) for pixel
+    // p in every lane of that pixel
+    const bool want_den = FEAT || agg != nullptr;
+    h8 ones;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ones[j] = (_Float16)1.0f;
+    f4 dh = {0.f, 0.f, 0.f, 0.f}, dl = {0.f, 0.f, 0.f, 0.f};
+    float den = 0.0f;
+    const float inv_scale = 1.0f / (CH == 3 ? 3.0f : 1.0f);
+    if constexpr (!CO) {
+        if (want_den) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                dh = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, whi[c], dh, 0, 0, 0);
+                dl = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, wlo[c], dl, 0, 0, 0);
+            }
+            den = dh[0] + dl[0];
+        }
+    }
+
+    // ---- running WTA over this lane's quarter of the disparity range ----
+    const float kInf = __builtin_inff();
+    float best = kInf, cm = kInf, cp = kInf, prev = kInf, first_v = kInf, last_v = kInf;
+    int bi = -1;
+    bool need_cp = false;
+    // FEAT: this lane's 8 lowest aggregated costs of its quarter, ascending
+    float tv[FEAT ? 8 : 1];
+    int tk[FEAT ? 8 : 1];
+    if constexpr (FEAT) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            tv[i] = kInf;
+            tk[i] = 0;
+        }
+    }
+
+    // Offset (halves) of octet 4c + gq of the group's union within a plane.
+    // It is periodic in c with period P = lcm(4, OPR) / 4 chunks (P chunks
+    // cover 4P / OPR whole union rows), so P lane-dependent bases plus
+    // compile-time row offsets address every chunk.
+    constexpr int P = (OPR == 3) ? 3 : 1;
+    static_assert(OPR == 1 || OPR == 2 || OPR == 3 || OPR == 4, "octets per row");
+    constexpr int kRowsPerPeriod = 4 * P / OPR;
+    int a_base[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        const int o = 4 * c + gq;
+        a_base[c] = (o / OPR) * LW + (o % OPR) * 8;
+    }
+    auto a_off = [&](int c) -> int {
+        if (4 * c + 3 < NOCT) return a_base[c % P] + (c / P) * kRowsPerPeriod * LW;
+        // last chunk: octets past the union carry zero weight; read the last real one
+        const int o = min(4 * c + gq, NOCT - 1);
+        return (o / OPR) * LW + (o % OPR) * 8;
+    };
+    constexpr int kOct = LW / 8;
+    const _Float16 hcap = (_Float16)scap;
+    const h2 cap2 = {hcap, hcap};
+
+    // Cost planes of blocks b0 .. b0+nbb-1: plane p = 16*bb + 4*gm + jm holds
+    // disparity index k = gm*Q + 4*(b0+bb) + jm.  An item is one octet (8
+    // positions of a tile row) at the 4 consecutive disparities jm = 0..3 of
+    // one (bb, gm).  Costs of positions off the image or of padded disparities
+    // are never weighted, so any finite value will do there.
+    auto build_slab = [&](int b0, int nbb) {
+        const int items = 4 * nbb * LH * kOct;
+#pragma unroll 1
+        for (int it = tid; it < items; it += kThreads) {
+            const int oc = it % kOct;
+            const int t = it / kOct;
+            const int row = t % LH;
+            const int quad = t / LH;                      // 4*bb + gm
+            const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
+            const int x0 = ox + 8 * oc;
+            _Float16* dst = s_cost + (size_t)(4 * quad) * PS + row * LW + 8 * oc;
+            if (CH == 1) {
+                const uint2 lv = *reinterpret_cast<const uint2*>(s_L + row * LWB + 8 * oc);
+                const h2 l0 = bytes01_f16(lv.x), l1 = bytes23_f16(lv.x);
+                const h2 l2 = bytes01_f16(lv.y), l3 = bytes23_f16(lv.y);
+#pragma unroll
+                for (int jm = 0; jm < 4; ++jm) {
+                    const int d = g.dmin + min(k0 + jm, D - 1);
+                    uint32_t r[2];
+                    load_unaligned<2>(s_R, row * RWB + 8 * oc + (dmax - d), r);
+                    const h2 c0 = __builtin_elementwise_min(__builtin_elementwise_abs(l0 - bytes01_f16(r[0])), cap2);
+                    const h2 c1 = __builtin_elementwise_min(__builtin_elementwise_abs(l1 - bytes23_f16(r[0])), cap2);
+                    const h2 c2 = __builtin_elementwise_min(__builtin_elementwise_abs(l2 - bytes01_f16(r[1])), cap2);
+                    const h2 c3 = __builtin_elementwise_min(__builtin_elementwise_abs(l3 - bytes23_f16(r[1])), cap2);
+                    h8 out = {c0[0], c0[1], c1[0], c1[1], c2[0], c2[1], c3[0], c3[1]};
+                    const int thr = d - x0;                       // positions j < thr: x - d < 0
+                    if (thr > 0) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            if (j < thr) out[j] = hcap;
+                    }
+                    *reinterpret_cast<h8*>(dst + jm * PS) = out;
+                }
+            } else {
+                const uint2* lq = reinterpret_cast<const uint2*>(s_L + row * LWB + 24 * oc);
+                const uint2 a0 = lq[0], a1 = lq[1], a2 = lq[2];
+                const uint32_t la[6] = {a0.x, a0.y, a1.x, a1.y, a2.x, a2.y};
+                uint32_t lpx[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) lpx[j] = rgb_pixel(la, j);
+#pragma unroll
+                for (int jm = 0; jm < 4; ++jm) {
+                    const int d = g.dmin + min(k0 + jm, D - 1);
+                    uint32_t ra[6];
+                    load_unaligned<6>(s_R, row * RWB + 24 * oc + 3 * (dmax - d), ra);
+                    uint32_t sad[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) sad[j] = __builtin_amdgcn_sad_u8(lpx[j], rgb_pixel(ra, j), 0u);
+                    h8 out;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const h2 c = __builtin_elementwise_min(small_int_pair(sad[2 * i], sad[2 * i + 1]), cap2);
+                        out[2 * i] = c[0];
+                        out[2 * i + 1] = c[1];
+                    }
+                    const int thr = d - x0;
+                    if (thr > 0) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            if (j < thr) out[j] = hcap;
+                    }
+                    *reinterpret_cast<h8*>(dst + jm * PS) = out;
+                }
+            }
+        }
+    };
+
+    // WTA (and agg_out / features) over the 4 rows j of one 16-disparity
+    // block: lane holds rows 4*gq + j of the 16x16 result, i.e. disparity
+    // index k = kb + j of pixel n
+    auto wta_block = [&](int kb, const f4& acc_h, const f4& acc_l) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = kb + j;
+            if (k < D) {
+                const float v = acc_h[j] + acc_l[j];
+                if (k == gq * Q) first_v = v;
+                last_v = v;
+                const bool lt = v < best;
+                if (lt) {
+                    cm = prev;
+                    best = v;
+                    bi = k;
+                } else if (need_cp) {
+                    cp = v;
+                }
+                need_cp = lt;
+                prev = v;
+                if (agg && pin)
+                    agg[(size_t)k * g.W * g.H + (size_t)py * g.W + px] = (v / den) * inv_scale;
+                if constexpr (FEAT) {
+                    // k rises within a quarter: insert after equal values
+                    const float a = (v / den) * inv_scale;
+                    if (a < tv[7]) {
+#pragma unroll
+                        for (int i = 7; i >= 0; --i) {
+                            const bool shift = i > 0 && a < tv[i > 0 ? i - 1 : 0];
+                            if (shift) {
+                                tv[i] = tv[i - 1];
+                                tk[i] = tk[i - 1];
+                            } else if (a < tv[i]) {
+                                tv[i] = a;
+                                tk[i] = k;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    };
+
+    const _Float16* plane0 = s_cost + (size_t)n * PS + grow0 * LW + gcol0;
+    if constexpr (CO) {
+        __syncthreads();
+        build_slab(0, nblk);
+        __syncthreads();
+        f4 ah[kCoMax], al[kCoMax];
+#pragma unroll
+        for (int b = 0; b < kCoMax; ++b) {
+            ah[b] = f4{0.f, 0.f, 0.f, 0.f};
+            al[b] = ah[b];
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            h8 wh, wl;
+            chunk_weights(c, wh, wl);
+            if (want_den) {
+                dh = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, wh, dh, 0, 0, 0);
+                dl = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, wl, dl, 0, 0, 0);
+            }
+            h8 a[kCoMax];
+#pragma unroll
+            for (int b = 0; b < kCoMax; ++b)
+                if (b < nblk) a[b] = lds_h8<GW == 8>(plane0 + (size_t)(16 * b) * PS + a_off(c));
+#pragma unroll
+            for (int b = 0; b < kCoMax; ++b)
+                if (b < nblk) ah[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[b], wh, ah[b], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < kCoMax; ++b)
+                if (b < nblk) al[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[b], wl, al[b], 0, 0, 0);
+        }
+        if (want_den) den = dh[0] + dl[0];
+#pragma unroll
+        for (int b = 0; b < kCoMax; ++b)
+            if (b < nblk) wta_block(gq * Q + 4 * b, ah[b], al[b]);
+    } else {
+        const int nslab = (nblk + nb - 1) / nb;
+        for (int s = 0; s < nslab; ++s) {
+            const int b0 = s * nb;
+            const int nbb = min(nb, nblk - b0);
+            __syncthreads();  // every wave is done with the previous slab
+            build_slab(b0, nbb);
+            __syncthreads();
+            // blocks in pairs: two independent hi and two lo chains
+#pragma unroll 1
+            for (int bb = 0; bb < nbb; bb += 2) {
+                const bool two = bb + 1 < nbb;
+                f4 ah0 = {0.f, 0.f, 0.f, 0.f}, al0 = ah0, ah1 = ah0, al1 = ah0;
+                const _Float16* p0 = plane0 + (size_t)(16 * bb) * PS;
+                const _Float16* p1 = p0 + (size_t)16 * PS;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const h8 a0 = lds_h8<GW == 8>(p0 + a_off(c));
+                    ah0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, whi[c], ah0, 0, 0, 0);
+                    al0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, wlo[c], al0, 0, 0, 0);
+                    if (two) {
+                        const h8 a1 = lds_h8<GW == 8>(p1 + a_off(c));
+                        ah1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, whi[c], ah1, 0, 0, 0);
+                        al1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, wlo[c], al1, 0, 0, 0);
+                    }
+                }
+                wta_block(gq * Q + 4 * (b0 + bb), ah0, al0);
+                if (two) wta_block(gq * Q + 4 * (b0 + bb + 1), ah1, al1);
+            }
+        }
+    }
+
+    // ---- merge the four quarters of pixel n (lanes n, n+16, n+32, n+48) ----
+    // quarter t covers disparity indices [t*Q, (t+1)*Q); the first minimum is
+    // the lowest quarter holding the smallest value
+    float wv = __shfl(best, n), wm = __shfl(cm, n), wp = __shfl(cp, n);
+    int wk = __shfl(bi, n), wc = __shfl((int)need_cp, n), wt = 0;
+    float left_last = kInf;   // last value of the quarter before the winner
+    float prev_last = __shfl(last_v, n);
+#pragma unroll
+    for (int t = 1; t < 4; ++t) {
+        const int src = n + 16 * t;
+        const float tv = __shfl(best, src);
+        const int tk = __shfl(bi, src);
+        const float tm = __shfl(cm, src), tp = __shfl(cp, src);
+        const int tc = __shfl((int)need_cp, src);
+        const bool take = tk >= 0 && tv < wv;
+        if (take) {
+            wv = tv; wk = tk; wm = tm; wp = tp; wc = tc; wt = t;
+            left_last = prev_last;
+        }
+        prev_last = __shfl(last_v, src);
+    }
+    // first value of the quarter after the winner
+    const float right_first = __shfl(first_v, n + 16 * min(wt + 1, 3));
+    if (gq == 0 && pin) {
+        float fm = wm, fp = wp;
+        if (wk == wt * Q && wt > 0) fm = left_last;
+        if (wc && wt < 3 && wk + 1 < D) fp = right_first;
+        const float ds = eq10_subpixel(g.dmin + wk, wk > 0 && wk < D - 1, fm, wv, fp);
+        const size_t o = (size_t)py * g.W + px;
+        if (disp) disp[o] = g.dmin + wk;
+        if (sub) sub[o] = ds;
+    }
+    if constexpr (FEAT) {
+        // merge the four quarters' sorted lists: 8 rounds, each taking the
+        // smallest head (the lower quarter, hence the lower d, on a tie)
+        uint32_t fw[8];
+        const float dn = (float)(D - 1);
+#pragma unroll
+        for (int rnd = 0; rnd < 8; ++rnd) {
+            float bvv = __shfl(tv[0], n);
+            int bkk = __shfl(tk[0], n), bt = 0;
+#pragma unroll
+            for (int t = 1; t < 4; ++t) {
+                const float v = __shfl(tv[0], n + 16 * t);
+                const int k = __shfl(tk[0], n + 16 * t);
+                if (v < bvv) {
+                    bvv = v;
+                    bkk = k;
+                    bt = t;
+                }
+            }
+            if (gq == bt) {
+#pragma unroll
+                for (int i = 0; i < 7; ++i) {
+                    tv[i] = tv[i + 1];
+                    tk[i] = tk[i + 1];
+                }
+                tv[7] = kInf;
+            }
+            const uint32_t cb = bf16_bits(bvv / g.tau), ib = bf16_bits((float)bkk / dn);
+            if (rnd & 1) {
+                fw[rnd >> 1] |= cb << 16;
+                fw[4 + (rnd >> 1)] |= ib << 16;
+            } else {
+                fw[rnd >> 1] = cb;
+                fw[4 + (rnd >> 1)] = ib;
+            }
+        }
+        if (gq == 0 && pin) {
+            const uint32_t lb = bf16_bits((float)lp[0] / 255.0f);
+            uint4* dst = reinterpret_cast<uint4*>(job.feat + ((size_t)py * g.W + px) * 32);
+            dst[0] = make_uint4(fw[0], fw[1], fw[2], fw[3]);
+            dst[1] = make_uint4(fw[4], fw[5], fw[6], fw[7]);
+            dst[2] = make_uint4(lb, 0u, 0u, 0u);
+            dst[3] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+}
+
+__device__ __forceinline__ void load_tables(const Tables& tb, int R, unsigned char* smem, int nthreads)
+{
+    float* s = reinterpret_cast<float*>(smem);
+    for (int i = threadIdx.x; i < kLutN; i += nthreads) s[i] = i < 511 ? tb.gr[abs(i - 255)] : 0.0f;
+    if (threadIdx.x < 32) s[kLutN + threadIdx.x] = (threadIdx.x <= R) ? tb.gs[threadIdx.x] : 0.0f;
+}
+
+// One workgroup per tile of one frame.
+template <int R, int CH, int NW, bool CO>
+__global__ __launch_bounds__(64 * NW) void k_fbs_mfma(TileJob job, Tables tb)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    load_tables(tb, R, smem, 64 * NW);
+    __syncthreads();
+    mfma_tile<R, CH, NW, false, CO>(job, blockIdx.x, blockIdx.y, smem, threadIdx.x);
+}
+
+// One workgroup per tile of one gray frame, with the surrogate's features.
+template <int R, int NW, bool CO>
+__global__ __launch_bounds__(64 * NW) void k_fbs_mfma_feat(TileJob job, Tables tb)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    load_tables(tb, R, smem, 64 * NW);
+    __syncthreads();
+    mfma_tile<R, 1, NW, true, CO>(job, blockIdx.x, blockIdx.y, smem, threadIdx.x);
+}
+
+// Persistent workgroups over a queue of (pair, tile) items of many frames of
+// one radius / channel class.  Every workgroup pops items until the queue is
+// empty, so every wave reaches the end.
+template <int R, int CH, int NW, bool CO>
+__global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __restrict__ pairs,
+                                                            const int2* __restrict__ items,
+                                                            int n_items, int* __restrict__ counter,
+                                                            const uint8_t* const* __restrict__ Ls,
+                                                            const uint8_t* const* __restrict__ Rs,
+                                                            int32_t* const* __restrict__ disps,
+                                                            float* const* __restrict__ subs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_next[2];
+    constexpr int kThreads = 64 * NW;
+    if (threadIdx.x == 0) s_next[0] = atomicAdd(counter, 1);
+    int buf = 0, cur_pair = -1;
+    for (;;) {
+        __syncthreads();   // s_next[buf] visible; every wave is done with the previous tile
+        // uniform across the workgroup: keep the item, its pair and geometry
+        // in scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(s_next[buf]);
+        if (it >= n_items) break;
+        // claim the next item now so the atomic's round trip overlaps this tile
+        if (threadIdx.x == 0) s_next[buf ^ 1] = atomicAdd(counter, 1);
+        buf ^= 1;
+        const int2 w = items[it];
+        const BatchPair& bp = pairs[w.x];
+        if (w.x != cur_pair) {   // items are grouped by pair: reload tables only on a change
+            load_tables(bp.tb, R, smem, kThreads);
+            cur_pair = w.x;
+            __syncthreads();
+        }
+        TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr, nullptr};
+        // an opaque copy of the thread index per item keeps the compiler from
+        // hoisting the tile's index arithmetic out of the loop (it would stay
+        // live in registers across every item)
+        int tid;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+        mfma_tile<R, CH, NW, false, CO>(job, w.y % bp.tiles_x, w.y / bp.tiles_x, smem, tid);
+    }
+}
+
+// One workgroup per (pair, tile) item of one class: the same tile code as
+// the per-frame kernel, the item taken from blockIdx.
+template <int R, int CH, int NW, bool CO>
+__global__ __launch_bounds__(64 * NW) void k_fbs_mfma_items(const BatchPair* __restrict__ pairs,
+                                                            const int2* __restrict__ items,
+                                                            const uint8_t* const* __restrict__ Ls,
+                                                            const uint8_t* const* __restrict__ Rs,
+                                                            int32_t* const* __restrict__ disps,
+                                                            float* const* __restrict__ subs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 w = items[blockIdx.x];
+    const BatchPair& bp = pairs[w.x];
+    load_tables(bp.tb, R, smem, 64 * NW);
+    __syncthreads();
+    TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr, nullptr};
+    mfma_tile<R, CH, NW, false, CO>(job, w.y % bp.tiles_x, w.y / bp.tiles_x, smem, threadIdx.x);
+}
+
+constexpr int kLdsLimit = 160 * 1024;  // per workgroup and per CU on gfx950
+constexpr int kMaxNb = 16;             // disparity blocks per slab
+constexpr int kMaxR12 = 7;  // largest radius built with 12-wave workgroups
+
+// deepest slab (>= 1) whose layout fits `budget` bytes
+inline int deepest_nb(const Geom& g, int nw, int budget)
+{
+    const int nblk = (g.D + 15) >> 4;
+    int nb = 1;
+    while (nb < nblk && nb < kMaxNb && mfma_layout(g.r, g.C, g.D, nb + 1, nw).bytes <= budget) ++nb;
+    return nb;
+}
+
+inline int max_nb(int r, int ch, int D, int nw)
+{
+    const int nblk = (D + 15) >> 4;
+    int nb = 1;
+    while (nb < nblk && nb < kMaxNb && mfma_layout(r, ch, D, nb + 1, nw).bytes <= kLdsLimit) ++nb;
+    return nb;
+}
+
+// the chunk-outer path applies when one slab holds every disparity block
+__host__ __device__ constexpr bool use_co(int D, int nb)
+{
+    return nb == ((D + 15) >> 4) && nb <= kCoMax;
+}
+
+template <int R, int CH, int NW>
+hipError_t launch_frame(const TileJob& job, const Tables& t, hipStream_t s)
+{
+    const MfmaLayout lay = mfma_layout(R, CH, job.g.D, job.nb, NW);
+    if (lay.bytes > kLdsLimit) return hipErrorInvalidConfiguration;
+    dim3 grid((job.g.W + 2 * NW - 1) / (2 * NW), (job.g.H + kTileH - 1) / kTileH);
+    if (use_co(job.g.D, job.nb))
+        hipLaunchKernelGGL((k_fbs_mfma<R, CH, NW, true>), grid, dim3(64 * NW), lay.bytes, s, job, t);
+    else
+        hipLaunchKernelGGL((k_fbs_mfma<R, CH, NW, false>), grid, dim3(64 * NW), lay.bytes, s, job, t);
+    return hipGetLastError();
+}
+
+template <int R, int CH, int NW>
+struct FeatOccupancy {
+    static hipError_t run(int lds, bool co, int* blocks)
+    {
+        if constexpr (CH != 1 || NW != 8) {
+            return hipErrorInvalidValue;
+        } else {
+            if (co)
+                return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    blocks, k_fbs_mfma_feat<R, NW, true>, 64 * NW, lds);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                blocks, k_fbs_mfma_feat<R, NW, false>, 64 * NW, lds);
+        }
+    }
+};
+
+// FeatOccupancy through the (r, ch, nw) dispatcher: only (gray, 8 waves) exists
+template <int R, int CH, int NW>
+struct FeatOccupancyAny {
+    static hipError_t run(int lds, bool co, int* blocks)
+    {
+        return FeatOccupancy<R, CH, NW>::run(lds, co, blocks);
+    }
+};
+
+template <int R, int CH, int NW>
+struct FeatLauncher {
+    static hipError_t run(const TileJob& job, const Tables& t, hipStream_t s)
+    {
+        if constexpr (CH != 1 || NW != 8) {
+            return hipErrorInvalidValue;
+        } else {
+            const MfmaLayout lay = mfma_layout(R, 1, job.g.D, job.nb, NW);
+            if (lay.bytes > kLdsLimit) return hipErrorInvalidConfiguration;
+            dim3 grid((job.g.W + 2 * NW - 1) / (2 * NW), (job.g.H + kTileH - 1) / kTileH);
+            if (use_co(job.g.D, job.nb))
+                hipLaunchKernelGGL((k_fbs_mfma_feat<R, NW, true>), grid, dim3(64 * NW), lay.bytes,
+                                   s, job, t);
+            else
+                hipLaunchKernelGGL((k_fbs_mfma_feat<R, NW, false>), grid, dim3(64 * NW), lay.bytes,
+                                   s, job, t);
+            return hipGetLastError();
+        }
+    }
+};
+
+template <int R, int CH, int NW, bool CO>
+hipError_t launch_batch_co(const BatchClass& bc, hipStream_t s)
+{
+    if (bc.one_wg_per_item) {
+        if (bc.n_items < 1) return hipSuccess;
+        hipLaunchKernelGGL((k_fbs_mfma_items<R, CH, NW, CO>), dim3(bc.n_items), dim3(64 * NW),
+                           bc.lds, s, bc.pairs, bc.items, bc.L, bc.R, bc.disp, bc.sub);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_fbs_mfma_batch<R, CH, NW, CO>), dim3(bc.grid), dim3(64 * NW), bc.lds, s,
+                       bc.pairs, bc.items, bc.n_items, bc.counter, bc.L, bc.R, bc.disp, bc.sub);
+    return hipGetLastError();
+}
+
+template <int R, int CH, int NW>
+hipError_t launch_batch(const BatchClass& bc, hipStream_t s)
+{
+    if (bc.lds <= 0 || bc.lds > kLdsLimit) return hipErrorInvalidConfiguration;
+    return bc.co ? launch_batch_co<R, CH, NW, true>(bc, s) : launch_batch_co<R, CH, NW, false>(bc, s);
+}
+
+// (R, CH, NW) dispatch; F<R, CH, NW>::run(args...)
+template <template <int, int, int> class F, int CH, int NW, typename... A>
+hipError_t dispatch_r(int r, A&&... a)
+{
+    switch (r) {
+    case 1: return F<1, CH, NW>::run(a...);
+    case 2: return F<2, CH, NW>::run(a...);
+    case 3: return F<3, CH, NW>::run(a...);
+    case 4: return F<4, CH, NW>::run(a...);
+    case 5: return F<5, CH, NW>::run(a...);
+    case 6: return F<6, CH, NW>::run(a...);
+    case 7: return F<7, CH, NW>::run(a...);
+    default: break;
+    }
+    // 12-wave workgroups cap a wave at 168 registers: above r = 7 the tile
+    // spills, so those are not built
+    if constexpr (NW != 12) {
+        switch (r) {
+        case 8: return F<8, CH, NW>::run(a...);
+        case 9: return F<9, CH, NW>::run(a...);
+        case 10: return F<10, CH, NW>::run(a...);
+        default: break;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <template <int, int, int> class F, typename... A>
+hipError_t dispatch(int r, int ch, int nw, A&&... a)
+{
+    if (ch == 3) {
+        if (nw == 4) return dispatch_r<F, 3, 4>(r, a...);
+        if (nw == 12) return dispatch_r<F, 3, 12>(r, a...);
+        return dispatch_r<F, 3, 8>(r, a...);
+    }
+    if (nw == 4) return dispatch_r<F, 1, 4>(r, a...);
+    if (nw == 12) return dispatch_r<F, 1, 12>(r, a...);
+    return dispatch_r<F, 1, 8>(r, a...);
+}
+
+template <int R, int CH, int NW>
+struct FrameLauncher {
+    static hipError_t run(const TileJob& j, const Tables& t, hipStream_t s)
+    {
+        return launch_frame<R, CH, NW>(j, t, s);
+    }
+};
+
+template <int R, int CH, int NW>
+struct BatchLauncher {
+    static hipError_t run(const BatchClass& bc, hipStream_t s) { return launch_batch<R, CH, NW>(bc, s); }
+};
+
+template <int R, int CH, int NW>
+struct FrameOccupancy {
+    static hipError_t run(int lds, bool co, int* blocks)
+    {
+        if (co)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fbs_mfma<R, CH, NW, true>,
+                                                                64 * NW, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fbs_mfma<R, CH, NW, false>,
+                                                            64 * NW, lds);
+    }
+};
+
+template <int R, int CH, int NW>
+struct BatchOccupancy {
+    static hipError_t run(int lds, bool co, int* blocks)
+    {
+        if (co)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                blocks, k_fbs_mfma_batch<R, CH, NW, true>, 64 * NW, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            blocks, k_fbs_mfma_batch<R, CH, NW, false>, 64 * NW, lds);
+    }
+};
+
+// Cap as the kernel sees it: tau (gray) or 3 tau (RGB), which must be an
+// exact fp16 value so every cost is exact in the A operand.
+inline bool scaled_cap(const Geom& g, float* out)
+{
+    const double c = (g.C == 3 ? 3.0 : 1.0) * (double)g.tau;
+    if (!(c > 0.0) || c > 2048.0) return false;
+    const _Float16 h = (_Float16)(float)c;
+    if ((double)(float)h != c) return false;
+    *out = (float)c;
+    return true;
+}
+
+template <template <int, int, int> class Occ>
+bool pick_cfg(const Geom& g, const int* cands, int ncands, MfmaCfg* out)
+{
+    const int nblk = (g.D + 15) >> 4;
+    int best = -1;
+    bool best_co = false;
+    for (int i = 0; i < ncands; ++i) {
+        const int cand = cands[i];
+        if (!mfma_nw_valid(g, cand)) continue;
+        int blocks = 0, nb = 0;
+        bool co = false;
+        if (nblk <= kCoMax && mfma_layout(g.r, g.C, g.D, nblk, cand).bytes <= kLdsLimit &&
+            dispatch<Occ>(g.r, g.C, cand, mfma_layout(g.r, g.C, g.D, nblk, cand).bytes, true,
+                          &blocks) == hipSuccess &&
+            blocks >= 1) {
+            nb = nblk;
+            co = true;
+        } else {
+            blocks = 0;
+            if (dispatch<Occ>(g.r, g.C, cand, mfma_layout(g.r, g.C, g.D, 1, cand).bytes, false,
+                              &blocks) != hipSuccess ||
+                blocks < 1)
+                continue;
+            nb = deepest_nb(g, cand, kLdsLimit / blocks);
+            if (use_co(g.D, nb)) nb = std::max(1, nb - 1);   // that path was not chosen above
+        }
+        const int waves = blocks * cand;
+        if (waves > best || (waves == best && co && !best_co)) {
+            best = waves;
+            best_co = co;
+            *out = MfmaCfg{cand, nb};
+        }
+    }
+    return best > 0;
+}
+
+}  // namespace
+}  // namespace fbs
