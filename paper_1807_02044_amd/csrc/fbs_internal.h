@@ -79,7 +79,6 @@ struct BatchPair {
     int nb;
     int tiles_x;
     int pad;
-    Tables tb;
 };
 
 // One persistent launch: every (pair, tile) item of one (radius, channels,
@@ -91,6 +90,7 @@ struct BatchClass {
     int grid;             // persistent workgroups
     int one_wg_per_item;  // 1: one workgroup per item instead of persistent ones
     int co;               // 1: every pair's slab holds all its disparity blocks
+    Tables tb;            // weight tables, shared by every pair of the class
     const BatchPair* pairs;
     const int2* items;
     int n_items;

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -245,17 +246,24 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
     if (cache_dirty) write_cache(tune_cache_path, cache);
 
     // classes and their work lists (most expensive pairs first)
-    std::map<int, std::vector<int>> by_class;  // key r*1000 + ch*100 + nw/4*10 + co
+    // classes: (r*1000 + ch*100 + nw/4*10 + co, sigma_s bits, sigma_r bits) - the
+    // pairs of a class share one kernel and one set of weight tables
+    std::map<std::tuple<int, uint32_t, uint32_t>, std::vector<int>> by_class;
     for (int i = 0; i < n; ++i)
         if (p->mfma[i]) {
             const Geom g = api_geom(&params[i]);
             const int co = mfma_use_co(g.D, p->cfg[i].nb) ? 1 : 0;
-            by_class[g.r * 1000 + g.C * 100 + p->cfg[i].nw / 4 * 10 + co].push_back(i);
+            uint32_t ss, sr;
+            memcpy(&ss, &params[i].sigma_s, 4);
+            memcpy(&sr, &params[i].sigma_r, 4);
+            by_class[std::make_tuple(g.r * 1000 + g.C * 100 + p->cfg[i].nw / 4 * 10 + co, ss, sr)]
+                .push_back(i);
         }
     std::vector<BatchPair> pairs(n);
     std::vector<int2> items;
     struct Span {
         int r, ch, nw, co, first, count, lds;
+        Tables tb;
     };
     std::vector<Span> spans;
     for (auto& kv : by_class) {
@@ -264,8 +272,9 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
             const Geom ga = api_geom(&params[a]), gb = api_geom(&params[b]);
             return ga.D > gb.D;  // cost per tile grows with D
         });
-        Span sp{kv.first / 1000, (kv.first / 100) % 10, ((kv.first / 10) % 10) * 4, kv.first % 10,
-                (int)items.size(), 0, 0};
+        const int key = std::get<0>(kv.first);
+        Span sp{key / 1000, (key / 100) % 10, ((key / 10) % 10) * 4, key % 10, (int)items.size(), 0, 0,
+                api_tables(&params[ids[0]])};
         for (int i : ids) {
             const Geom g = api_geom(&params[i]);
             const int tw = 2 * p->cfg[i].nw;
@@ -276,7 +285,6 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
             pairs[i].nb = p->cfg[i].nb;
             pairs[i].tiles_x = tx;
             pairs[i].pad = 0;
-            pairs[i].tb = api_tables(&params[i]);
             // each tile lays out LDS for its own pair's D and slab depth
             sp.lds = std::max(sp.lds, mfma_lds_bytes(g, p->cfg[i].nb, p->cfg[i].nw));
         }
@@ -314,6 +322,7 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
         bc.nw = sp.nw;
         bc.lds = sp.lds;
         bc.co = sp.co;
+        bc.tb = sp.tb;
         const int per_cu = mfma_batch_blocks_per_cu(sp.r, sp.ch, sp.nw, sp.lds, sp.co != 0);
         bc.grid = std::max(1, std::min(sp.count, cus * per_cu));
         bc.one_wg_per_item = (flags & FBS_PLAN_PER_TILE) ? 1 : 0;

@@ -716,7 +716,7 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_feat(TileJob job, Tables t
 }
 
 // Persistent workgroups over a queue of (pair, tile) items of many frames of
-// one radius / channel class.  Every workgroup pops items until the queue is
+// one class (radius, channels, waves, path and weight tables).  Every workgroup pops items until the queue is
 // empty, so every wave reaches the end.
 template <int R, int CH, int NW, bool CO>
 __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __restrict__ pairs,
@@ -725,13 +725,15 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __r
                                                             const uint8_t* const* __restrict__ Ls,
                                                             const uint8_t* const* __restrict__ Rs,
                                                             int32_t* const* __restrict__ disps,
-                                                            float* const* __restrict__ subs)
+                                                            float* const* __restrict__ subs,
+                                                            Tables tb)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_next[2];
     constexpr int kThreads = 64 * NW;
+    load_tables(tb, R, smem, kThreads);   // the class shares its weight tables
     if (threadIdx.x == 0) s_next[0] = atomicAdd(counter, 1);
-    int buf = 0, cur_pair = -1;
+    int buf = 0;
     for (;;) {
         __syncthreads();   // s_next[buf] visible; every wave is done with the previous tile
         // uniform across the workgroup: keep the item, its pair and geometry
@@ -743,11 +745,6 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __r
         buf ^= 1;
         const int2 w = items[it];
         const BatchPair& bp = pairs[w.x];
-        if (w.x != cur_pair) {   // items are grouped by pair: reload tables only on a change
-            load_tables(bp.tb, R, smem, kThreads);
-            cur_pair = w.x;
-            __syncthreads();
-        }
         TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr, nullptr};
         // an opaque copy of the thread index per item keeps the compiler from
         // hoisting the tile's index arithmetic out of the loop (it would stay
@@ -766,12 +763,13 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_items(const BatchPair* __r
                                                             const uint8_t* const* __restrict__ Ls,
                                                             const uint8_t* const* __restrict__ Rs,
                                                             int32_t* const* __restrict__ disps,
-                                                            float* const* __restrict__ subs)
+                                                            float* const* __restrict__ subs,
+                                                            Tables tb)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    load_tables(tb, R, smem, 64 * NW);   // the class shares its weight tables
     const int2 w = items[blockIdx.x];
     const BatchPair& bp = pairs[w.x];
-    load_tables(bp.tb, R, smem, 64 * NW);
     __syncthreads();
     TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr, nullptr};
     mfma_tile<R, CH, NW, false, CO>(job, w.y % bp.tiles_x, w.y / bp.tiles_x, smem, threadIdx.x);
@@ -869,11 +867,12 @@ hipError_t launch_batch_co(const BatchClass& bc, hipStream_t s)
     if (bc.one_wg_per_item) {
         if (bc.n_items < 1) return hipSuccess;
         hipLaunchKernelGGL((k_fbs_mfma_items<R, CH, NW, CO>), dim3(bc.n_items), dim3(64 * NW),
-                           bc.lds, s, bc.pairs, bc.items, bc.L, bc.R, bc.disp, bc.sub);
+                           bc.lds, s, bc.pairs, bc.items, bc.L, bc.R, bc.disp, bc.sub, bc.tb);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_fbs_mfma_batch<R, CH, NW, CO>), dim3(bc.grid), dim3(64 * NW), bc.lds, s,
-                       bc.pairs, bc.items, bc.n_items, bc.counter, bc.L, bc.R, bc.disp, bc.sub);
+                       bc.pairs, bc.items, bc.n_items, bc.counter, bc.L, bc.R, bc.disp, bc.sub,
+                       bc.tb);
     return hipGetLastError();
 }
 

@@ -159,18 +159,28 @@ def _max_nb(params, wl, tmp_path, nw):
 
 def test_plan_class_mixing_slab_depths(tmp_path):
     """One class (r = 10, 8 waves) holding a 64-disparity pair at its deepest
-    slab and two 256-disparity pairs at theirs (shallower): the launch must
-    size LDS for the largest per-pair layout, not for (largest D) x (deepest
-    slab), and every pair keeps fbs_run's bits."""
-    specs = [(80, 40, 0, 63), (300, 40, 0, 255), (310, 33, 2, 257)]
-    pairs = []
-    for i, (W, H, d0, d1) in enumerate(specs):
-        wl = scenes.Workload(f"m{i}", W, H, 1, d0, d1, 10, 10.0, 10.0, 40.0,
-                             scene="slanted", seed=700 + i, n_planes=3)
+    slab and two wider-range pairs at theirs (shallower, found by probing):
+    the launch must size LDS for the largest per-pair layout, not for
+    (largest D) x (deepest slab), and every pair keeps fbs_run's bits."""
+    def wl_of(i, W, H, d0, D):
+        return scenes.Workload(f"m{i}", W, H, 1, d0, d0 + D - 1, 10, 10.0, 10.0, 40.0,
+                               scene="slanted", seed=700 + i, n_planes=3)
+    small = wl_of(0, 80, 40, 0, 64)
+    nb_small = _max_nb(fbs.params_for(small), small, tmp_path, 8)
+    big_D = None
+    for D in (256, 512, 768, 1000):
+        w = wl_of(9, D + 40, 8, 0, D)
+        if _max_nb(fbs.params_for(w), w, tmp_path, 8) < nb_small:
+            big_D = D
+            break
+    assert big_D is not None, "no disparity range with a shallower deepest slab"
+    pairs = [(small, scenes.make_pair(small))]
+    for i, (extra_w, H, d0) in enumerate([(40, 24, 0), (50, 17, 2)], start=1):
+        wl = wl_of(i, big_D + extra_w + d0, H, d0, big_D)
         pairs.append((wl, scenes.make_pair(wl)))
     params = [fbs.params_for(wl) for wl, _ in pairs]
     nbs = [_max_nb(p, wl, tmp_path, 8) for p, (wl, _) in zip(params, pairs)]
-    _say("deepest slabs at 8 waves", nbs)
+    _say("deepest slabs at 8 waves", nbs, "big D", big_D)
     assert nbs[0] > nbs[1] >= 1 and nbs[2] >= 1
     cache = tmp_path / "tune.json"
     entries = {f"{wl.width},{wl.height},1,{wl.n_disp},10": [8, nb, 1.0]
