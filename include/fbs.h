@@ -259,6 +259,21 @@ fbs_status fbs_surrogate_run(fbs_surrogate* s, const fbs_params* cheap, const fb
                              const uint8_t* left, const uint8_t* right, float* disp_sub,
                              float gate_px, float gate_frac, int32_t* fell_back, void* stream);
 
+/* Inference with a fallback per tile: runs `cheap` and its features, then
+ * the net into disp_sub, then reruns `full` (same pair and disparity range)
+ * on every tile of the full run's matrix-core kernel (8 rows by 8, 16 or 24
+ * columns, as fbs_run picks for `full`) in which more than tile_frac of the
+ * pixels have |prediction - cheap subpixel map| > gate_px; those tiles of
+ * disp_sub then hold exactly fbs_run(full)'s values.  tile_frac < 0 reruns
+ * every tile, tile_frac >= 1 none.  No host synchronisation: the tile list
+ * is built and consumed on the device.  FBS_E_UNSUPPORTED when `full` is
+ * not a gray TAD run the matrix-core kernel takes (or forces the vector
+ * ALUs).  Calls on one object must not overlap. */
+fbs_status fbs_surrogate_run_tiled(fbs_surrogate* s, const fbs_params* cheap,
+                                   const fbs_params* full, const uint8_t* left,
+                                   const uint8_t* right, float* disp_sub, float gate_px,
+                                   float tile_frac, void* stream);
+
 /* Static description of a status code. */
 const char* fbs_status_str(int status);
 

@@ -42,7 +42,8 @@ EXPORTS = (
     "fbs_surrogate_create", "fbs_surrogate_destroy", "fbs_surrogate_set_params",
     "fbs_surrogate_get_params", "fbs_surrogate_features", "fbs_surrogate_cheap_run",
     "fbs_surrogate_forward",
-    "fbs_surrogate_gradients", "fbs_surrogate_adam", "fbs_surrogate_run", "fbs_status_str",
+    "fbs_surrogate_gradients", "fbs_surrogate_adam", "fbs_surrogate_run",
+    "fbs_surrogate_run_tiled", "fbs_status_str",
     "fbs_last_error", "fbs_version",
 )
 
@@ -132,11 +133,13 @@ def lib() -> ctypes.CDLL:
         h.fbs_surrogate_adam.argtypes = [vp, vp, ctypes.c_float, vp]
         h.fbs_surrogate_run.argtypes = [vp, P, P, vp, vp, vp, ctypes.c_float, ctypes.c_float,
                                         ctypes.POINTER(ctypes.c_int32), vp]
+        h.fbs_surrogate_run_tiled.argtypes = [vp, P, P, vp, vp, vp, ctypes.c_float,
+                                              ctypes.c_float, vp]
         for f in (h.fbs_surrogate_create, h.fbs_surrogate_set_params,
                   h.fbs_surrogate_get_params, h.fbs_surrogate_features,
                   h.fbs_surrogate_cheap_run,
                   h.fbs_surrogate_forward, h.fbs_surrogate_gradients, h.fbs_surrogate_adam,
-                  h.fbs_surrogate_run):
+                  h.fbs_surrogate_run, h.fbs_surrogate_run_tiled):
             f.restype = ctypes.c_int
         h.fbs_status_str.argtypes = [ctypes.c_int]
         h.fbs_status_str.restype = ctypes.c_char_p
@@ -322,6 +325,12 @@ class FbsSurrogate:
                                        _ptr(left), _ptr(right), _ptr(disp_sub), float(gate_px),
                                        float(gate_frac), ctypes.byref(fb), _stream(stream)))
         return bool(fb.value)
+
+    def run_tiled(self, cheap: FbsParams, full: FbsParams, left, right, disp_sub,
+                  gate_px: float, tile_frac: float, stream=None):
+        _check(lib().fbs_surrogate_run_tiled(self.handle, ctypes.byref(cheap), ctypes.byref(full),
+                                             _ptr(left), _ptr(right), _ptr(disp_sub),
+                                             float(gate_px), float(tile_frac), _stream(stream)))
 
     def close(self):
         if self.handle:

@@ -94,6 +94,7 @@ struct BatchClass {
     const BatchPair* pairs;
     const int2* items;
     int n_items;
+    const int* n_dev;     // non-null: the queue length is read from here (persistent only)
     int* counter;
     const uint8_t* const* L;
     const uint8_t* const* R;

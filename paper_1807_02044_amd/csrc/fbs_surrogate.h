@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fbs_internal.h"
+
 // Packed parameter order (float32): w0 [3][3][32][17], b0 [32], w1 [3][3][32][32],
 // b1 [32], w2 [3][3][32][32], b2 [32], w3 [3][3][1][32], b3 [1].
 #define SUR_CH 32
@@ -23,6 +25,15 @@
 #define SUR_BWD 1
 
 namespace fbs {
+// The full-radius job of a tile-gated surrogate run, as the fallback kernel
+// reads it: one pair and its image / output pointers.
+struct SurFallbackJob {
+    BatchPair pair;
+    const uint8_t* L;
+    const uint8_t* R;
+    int32_t* disp;
+    float* sub;
+};
 hipError_t sur_features(int W, int H, int D, float tau, const float* agg, const uint8_t* L,
                         int lstride, uint16_t* F, hipStream_t s);
 hipError_t sur_conv(int mode, int W, int H, const uint16_t* in, const uint16_t* A,
@@ -46,4 +57,12 @@ hipError_t sur_pack(const float* master, uint16_t* fwd, uint16_t* bwd, float* w3
                     hipStream_t s);
 hipError_t sur_gate(int n, const float* pred, const float* cheap, float gate_px, int* count,
                     hipStream_t s);
+// fused inference of the whole net; zero2 (nullable): two ints set to 0
+size_t sur_net_lds_bytes();
+hipError_t sur_net_fwd(int W, int H, const uint16_t* feat, const uint16_t* fwd, const float* bias,
+                       const float* w3, const float* b3, const float* cheap, float* pred,
+                       int* zero2, hipStream_t s);
+hipError_t sur_tile_gate(int W, int H, const float* pred, const float* cheap, float gate_px,
+                         float tile_frac, int tw, int2* items, int* n_items,
+                         const SurFallbackJob& job, SurFallbackJob* job_out, hipStream_t s);
 }  // namespace fbs

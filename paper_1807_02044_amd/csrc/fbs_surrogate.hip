@@ -50,6 +50,13 @@ struct fbs_surrogate {
     float *vol = nullptr, *cheap = nullptr;
     int* count = nullptr;
     int* h_count = nullptr;  // pinned
+    // tile-gated runs: listed fallback tiles, {list length, queue counter},
+    // the full-radius job as the fallback kernel reads it
+    int2* items = nullptr;
+    int* qctr = nullptr;
+    fbs::SurFallbackJob* job = nullptr;
+    int max_tiles = 0;
+    int cus = 0;
 };
 
 namespace {
@@ -67,7 +74,8 @@ void sur_free(fbs_surrogate* s)
     if (!s) return;
     void* ptrs[] = {s->master, s->m, s->v, s->grads, s->fwd, s->bwd, s->w3, s->bias, s->a1,
                     s->a2, s->a3, s->g2, s->g1, s->g0, s->feat, s->g4, s->loss_parts, s->part,
-                    s->red0, s->red1, s->red2, s->red3, s->vol, s->cheap, s->count};
+                    s->red0, s->red1, s->red2, s->red3, s->vol, s->cheap, s->count,
+                    s->items, s->qctr, s->job};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (s->h_count) (void)hipHostFree(s->h_count);
@@ -88,13 +96,19 @@ fbs_status hipst(hipError_t e, const char* what)
     return api_fail(FBS_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// forward of the three 32 -> 32 layers and the last layer (with the L1
-// gradient when label is given)
+// Forward of the three 32 -> 32 layers and the last layer.  Inference
+// (no label) is one fused kernel; with a label the layers run one by one,
+// keeping the activations for the backward pass, and the last layer also
+// forms the L1 gradient.  Both give the same bits.
 fbs_status forward(fbs_surrogate* s, int W, int H, const uint16_t* feat, const float* cheap,
-                   float* pred, const float* label, hipStream_t st)
+                   float* pred, const float* label, hipStream_t st, int* zero2 = nullptr)
 {
     using namespace fbs;
     constexpr int LW = 9 * SUR_CH * SUR_CH;
+    if (!label)
+        return hipst(sur_net_fwd(W, H, feat, s->fwd, s->bias, s->w3, s->master + SUR_OFF_B3, cheap,
+                                 pred, zero2, st),
+                     "surrogate forward");
     hipError_t e = sur_conv(SUR_FWD, W, H, feat, s->fwd, s->bias, nullptr, s->a1, st);
     if (e == hipSuccess) e = sur_conv(SUR_FWD, W, H, s->a1, s->fwd + LW, s->bias + SUR_CH, nullptr, s->a2, st);
     if (e == hipSuccess) e = sur_conv(SUR_FWD, W, H, s->a2, s->fwd + 2 * LW, s->bias + 2 * SUR_CH, nullptr, s->a3, st);
@@ -139,6 +153,13 @@ fbs_status fbs_surrogate_create(fbs_surrogate** out, int32_t max_width, int32_t 
               dalloc(&s->red2, SUR_PART) && dalloc(&s->red3, 9 * SUR_CH + 1) &&
               dalloc(&s->vol, N * max_disp) && dalloc(&s->cheap, N) && dalloc(&s->count, 1) &&
               hipHostMalloc(&s->h_count, sizeof(int), hipHostMallocDefault) == hipSuccess;
+    // fallback tiles are at least 8 x 8 pixels
+    s->max_tiles = ((max_width + 7) / 8) * ((max_height + 7) / 8);
+    ok = ok && dalloc(&s->items, s->max_tiles) && dalloc(&s->qctr, 2) && dalloc(&s->job, 1);
+    int dev = 0;
+    if (ok && hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (s->cus <= 0) s->cus = 256;
     if (!ok) {
         sur_free(s);
         return api_fail(FBS_E_HIP, "surrogate: device allocation failed");
@@ -295,9 +316,12 @@ fbs_status fbs_surrogate_adam(fbs_surrogate* s, const float* grads, float lr, vo
     return hipst(e, "surrogate adam");
 }
 
-fbs_status fbs_surrogate_run(fbs_surrogate* s, const fbs_params* cheap, const fbs_params* full,
-                             const uint8_t* left, const uint8_t* right, float* disp_sub,
-                             float gate_px, float gate_frac, int32_t* fell_back, void* stream)
+}  // extern "C"
+
+namespace {
+// arguments shared by the gated runs
+fbs_status check_pair(fbs_surrogate* s, const fbs_params* cheap, const fbs_params* full,
+                      const uint8_t* left, const uint8_t* right, float* disp_sub)
 {
     fbs_status st = fbs::api_check_params(cheap);
     if (st == FBS_OK) st = fbs::api_check_params(full);
@@ -310,6 +334,20 @@ fbs_status fbs_surrogate_run(fbs_surrogate* s, const fbs_params* cheap, const fb
         return api_fail(FBS_E_INVALID, "cheap and full runs must describe the same pair");
     if (D > s->max_d) return api_fail(FBS_E_INVALID, "%d disparities above the maximum %d", D, s->max_d);
     if (!left || !right || !disp_sub) return api_fail(FBS_E_INVALID, "left, right, disp_sub required");
+    if ((uintptr_t)disp_sub & 3u) return api_fail(FBS_E_INVALID, "disp_sub must be 4-byte aligned");
+    return FBS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+fbs_status fbs_surrogate_run(fbs_surrogate* s, const fbs_params* cheap, const fbs_params* full,
+                             const uint8_t* left, const uint8_t* right, float* disp_sub,
+                             float gate_px, float gate_frac, int32_t* fell_back, void* stream)
+{
+    fbs_status st = check_pair(s, cheap, full, left, right, disp_sub);
+    if (st != FBS_OK) return st;
+    const int W = cheap->width, H = cheap->height;
     if (!(gate_px >= 0.0f) || !(gate_frac >= 0.0f)) return api_fail(FBS_E_INVALID, "bad gate");
     hipStream_t q = (hipStream_t)stream;
     st = fbs_surrogate_cheap_run(s, cheap, left, right, s->cheap, s->feat, stream);
@@ -326,6 +364,62 @@ fbs_status fbs_surrogate_run(fbs_surrogate* s, const fbs_params* cheap, const fb
     if (fell_back) *fell_back = fb ? 1 : 0;
     if (fb) return fbs_run(full, left, right, nullptr, disp_sub, nullptr, nullptr, stream);
     return FBS_OK;
+}
+
+fbs_status fbs_surrogate_run_tiled(fbs_surrogate* s, const fbs_params* cheap,
+                                   const fbs_params* full, const uint8_t* left,
+                                   const uint8_t* right, float* disp_sub, float gate_px,
+                                   float tile_frac, void* stream)
+{
+    using namespace fbs;
+    fbs_status st = check_pair(s, cheap, full, left, right, disp_sub);
+    if (st != FBS_OK) return st;
+    if (!(gate_px >= 0.0f) || tile_frac != tile_frac) return api_fail(FBS_E_INVALID, "bad gate");
+    const Geom gf = api_geom(full);
+    if ((full->flags & FBS_F_FORCE_VALU) || full->cost_type != FBS_COST_TAD || !mfma_supported(gf))
+        return api_fail(FBS_E_UNSUPPORTED, "tile-gated runs need the matrix-core kernel for the full run");
+    const int W = cheap->width, H = cheap->height;
+    hipStream_t q = (hipStream_t)stream;
+    st = fbs_surrogate_cheap_run(s, cheap, left, right, s->cheap, s->feat, stream);
+    if (st != FBS_OK) return st;
+    (void)hipGetLastError();
+    // the net also clears the tile list and the fallback queue
+    st = forward(s, W, H, s->feat, s->cheap, disp_sub, nullptr, q, s->qctr);
+    if (st != FBS_OK) return st;
+    const MfmaCfg cfg = mfma_default_cfg(gf);
+    const int tw = 2 * cfg.nw, tiles_x = (W + tw - 1) / tw;
+    if (tiles_x * ((H + 7) / 8) > s->max_tiles) return api_fail(FBS_E_INVALID, "too many tiles");
+    SurFallbackJob job{};
+    job.pair.g = gf;
+    job.pair.scap = mfma_scaled_cap(gf);
+    job.pair.nb = cfg.nb;
+    job.pair.tiles_x = tiles_x;
+    job.L = left;
+    job.R = right;
+    job.disp = nullptr;
+    job.sub = disp_sub;
+    hipError_t e = sur_tile_gate(W, H, disp_sub, s->cheap, gate_px, tile_frac, tw, s->items,
+                                 s->qctr, job, s->job, q);
+    if (e != hipSuccess) return hipst(e, "surrogate tile gate");
+    BatchClass bc{};
+    bc.r = gf.r;
+    bc.ch = gf.C;
+    bc.nw = cfg.nw;
+    bc.co = mfma_use_co(gf.D, cfg.nb) ? 1 : 0;
+    bc.lds = mfma_lds_bytes(gf, cfg.nb, cfg.nw);
+    bc.tb = api_tables(full);
+    bc.grid = s->cus * mfma_batch_blocks_per_cu(gf.r, gf.C, cfg.nw, bc.lds, bc.co != 0);
+    bc.one_wg_per_item = 0;
+    bc.pairs = &s->job->pair;
+    bc.items = s->items;
+    bc.n_items = 0;
+    bc.n_dev = s->qctr;
+    bc.counter = s->qctr + 1;
+    bc.L = &s->job->L;
+    bc.R = &s->job->R;
+    bc.disp = &s->job->disp;
+    bc.sub = &s->job->sub;
+    return hipst(launch_mfma_batch(bc, q), "surrogate tile fallback");
 }
 
 }  // extern "C"

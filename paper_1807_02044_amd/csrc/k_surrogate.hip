@@ -17,6 +17,8 @@
 //   k_sur_adam         Adam on the float32 master weights
 //   k_sur_pack         BF16 kernel copies of the master weights
 //   k_sur_gate         count of pixels where prediction and cheap differ
+#include <algorithm>
+
 #include "fbs_internal.h"
 #include "fbs_surrogate.h"
 
@@ -165,6 +167,157 @@ __global__ __launch_bounds__(256) void k_sur_conv(int W, int H, const uint16_t* 
                     make_uint2((uint32_t)r[0] | ((uint32_t)r[1] << 16), (uint32_t)r[2] | ((uint32_t)r[3] << 16));
             }
         }
+    }
+}
+
+// ------------------------------------------------ fused inference (whole net)
+//
+// One workgroup: an NT x NT tile of predictions.  The tile's features plus a
+// 4-pixel halo (the receptive radius of four 3x3 layers) are staged in LDS;
+// each 32 -> 32 layer reads one LDS buffer and writes the other, its square
+// shrinking by one pixel per side (34 -> 32 -> 30 -> 28), and the 32 -> 1
+// layer reads the last one.  Activations of positions off the image are
+// stored as 0: every layer sees the zero padding of a 'same' convolution.
+//
+// LDS holds activations by channel octet: plane q keeps channels 8q..8q+7 of
+// every pixel in 16 bytes, so the 16 pixels of an MFMA B operand are 256
+// contiguous bytes (no bank conflicts).  A wave takes 16 columns x 4 rows of a
+// layer's output; each B operand (input row, column shift) it loads serves the
+// (up to) three output rows that use it.  Every output is summed in the same
+// order as in k_sur_conv / k_sur_last_fwd, so the predictions are
+// bit-identical to the per-layer kernels'.
+constexpr int NT = 26, NS0 = NT + 8;
+constexpr int kNetThreads = 512;
+constexpr int kPlaneA = NS0 * NS0, kPlaneB = (NS0 - 2) * (NS0 - 2);
+
+template <int SI>
+__device__ __forceinline__ void net_layer(const uint16_t* __restrict__ src, int srcP,
+                                          uint16_t* __restrict__ dst, int dstP,
+                                          const uint16_t* __restrict__ A,
+                                          const float* __restrict__ bias, int W, int H, int oy,
+                                          int ox, int lane, int wave)
+{
+    constexpr int SO = SI - 2, NSEG = (SO + 15) / 16, NSTRIP = (SO + 3) / 4;
+    const int m = lane & 15, kq = lane >> 4;
+    bf8 aw[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+            aw[t][cb] = *reinterpret_cast<const bf8*>(A + ((size_t)(t * kC + cb * 16 + m) * kC + 8 * kq));
+    float bs[2][4];  // this lane's output channels 16cb + 4kq + j
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bs[cb][j] = bias[cb * 16 + 4 * kq + j];
+    const uint16_t* plane = src + (size_t)kq * srcP * 8;
+#pragma unroll 1
+    for (int item = wave; item < NSEG * NSTRIP; item += kNetThreads / 64) {
+        const int seg = item % NSEG, r0 = (item / NSEG) * 4;
+        const int c = seg * 16 + m;  // output column of this lane (B / result column)
+        f4 acc[4][2];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int qi = 0; qi < 6; ++qi) {
+            const int q = r0 + qi;  // input row
+            if (q >= SI) break;
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                // columns past the output are computed from clamped reads and dropped
+                const int col = min(c + kx, SI - 1);
+                const bf8 b = *reinterpret_cast<const bf8*>(plane + (size_t)(q * SI + col) * 8);
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky) {
+                    const int r = qi - ky;  // output row r0 + r takes input row q as tap row ky
+                    if (r >= 0 && r < 4 && r0 + r < SO) {
+                        acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[3 * ky + kx][0], b, acc[r][0], 0, 0, 0);
+                        acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[3 * ky + kx][1], b, acc[r][1], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (c < SO) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (r0 + r >= SO) break;
+                const int y = oy + r0 + r, x = ox + c;
+                const bool in = x >= 0 && x < W && y >= 0 && y < H;
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    const int c0 = cb * 16 + 4 * kq;
+                    uint16_t v[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = in ? to_bf16(fmaxf(acc[r][cb][j] + bs[cb][j], 0.0f)) : 0;
+                    *reinterpret_cast<uint2*>(dst + ((size_t)(c0 >> 3) * dstP + (r0 + r) * SO + c) * 8 + (c0 & 7)) =
+                        make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16));
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kNetThreads) void k_sur_net_fwd(int W, int H, const uint16_t* __restrict__ feat,
+                                                             const uint16_t* __restrict__ fwd,
+                                                             const float* __restrict__ bias,
+                                                             const float* __restrict__ w3,
+                                                             const float* __restrict__ b3,
+                                                             const float* __restrict__ cheap,
+                                                             float* __restrict__ pred,
+                                                             int* __restrict__ zero2)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* bufA = reinterpret_cast<uint16_t*>(smem);
+    uint16_t* bufB = bufA + (size_t)kPlaneA * kC;
+    float* s_w3 = reinterpret_cast<float*>(bufB + (size_t)kPlaneB * kC);
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int i = tid; i < 9 * kC; i += kNetThreads) s_w3[i] = w3[i];
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (zero2 && blockIdx.x == 0 && blockIdx.y == 0 && tid < 2) zero2[tid] = 0;
+    const int X0 = blockIdx.x * NT - 4, Y0 = blockIdx.y * NT - 4;  // image position of bufA's origin
+    for (int i = tid; i < kPlaneA * 4; i += kNetThreads) {
+        const int px = i >> 2, q = i & 3;
+        const int ty = px / NS0, tx = px - ty * NS0;
+        const int y = Y0 + ty, x = X0 + tx;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (x >= 0 && x < W && y >= 0 && y < H)
+            v = reinterpret_cast<const uint4*>(feat + ((size_t)y * W + x) * kC)[q];
+        reinterpret_cast<uint4*>(bufA)[(size_t)q * kPlaneA + px] = v;
+    }
+    __syncthreads();
+    constexpr int LW = 9 * kC * kC;
+    net_layer<NS0>(bufA, kPlaneA, bufB, kPlaneB, fwd, bias, W, H, Y0 + 1, X0 + 1, lane, wave);
+    __syncthreads();
+    net_layer<NS0 - 2>(bufB, kPlaneB, bufA, kPlaneA, fwd + LW, bias + kC, W, H, Y0 + 2, X0 + 2, lane, wave);
+    __syncthreads();
+    net_layer<NS0 - 4>(bufA, kPlaneA, bufB, kPlaneB, fwd + 2 * LW, bias + 2 * kC, W, H, Y0 + 3, X0 + 3, lane, wave);
+    __syncthreads();
+    // 32 -> 1 layer and the residual; bufB holds layer 3 on a 28-pixel square
+    constexpr int S3 = NS0 - 6;
+    for (int i = tid; i < NT * NT; i += kNetThreads) {
+        const int r = i / NT, c = i - r * NT;
+        const int y = Y0 + 4 + r, x = X0 + 4 + c;
+        if (x >= W || y >= H) continue;
+        float acc = *b3;
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t - 3 * ky;
+            const int yy = y + ky - 1, xx = x + kx - 1;
+            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+            const int px = (r + ky) * S3 + (c + kx);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint4 v = reinterpret_cast<const uint4*>(bufB)[(size_t)q * kPlaneB + px];
+                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ch = 8 * q + 2 * e;
+                    acc = fmaf(s_w3[t * kC + ch], from_bf16((uint16_t)(u[e] & 0xffff)), acc);
+                    acc = fmaf(s_w3[t * kC + ch + 1], from_bf16((uint16_t)(u[e] >> 16)), acc);
+                }
+            }
+        }
+        const size_t o = (size_t)y * W + x;
+        pred[o] = cheap[o] + acc;
     }
 }
 
@@ -445,17 +598,64 @@ __global__ __launch_bounds__(256) void k_sur_unpack_grads(const float* __restric
 
 __global__ void k_sur_zero(int* p) { *p = 0; }
 
+// grid-stride count; one atomic per workgroup
 __global__ __launch_bounds__(256) void k_sur_gate(int n, const float* __restrict__ pred,
                                                   const float* __restrict__ cheap, float gate_px,
                                                   int* __restrict__ count)
 {
-    __shared__ int s_c;
-    if (threadIdx.x == 0) s_c = 0;
+    __shared__ int s_c[4];
+    int c = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+        c += fabsf(pred[i] - cheap[i]) > gate_px ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = c;
     __syncthreads();
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n && fabsf(pred[i] - cheap[i]) > gate_px) atomicAdd(&s_c, 1);
+    if (threadIdx.x == 0) {
+        const int t = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+        if (t) atomicAdd(count, t);
+    }
+}
+
+// Sixteen lanes per fallback tile (tw x 8 pixels of the full-radius run), 16
+// tiles per workgroup: a tile is listed when more than tile_frac of its
+// pixels in the image have |pred - cheap| > gate_px.  One atomic per
+// workgroup reserves the list slots.  Block 0 also publishes the full-radius
+// job for the fallback kernel.  n_items and the fallback's queue counter
+// start at 0 (cleared by k_sur_net_fwd).
+__global__ __launch_bounds__(256) void k_sur_tile_gate(int W, int H, const float* __restrict__ pred,
+                                                       const float* __restrict__ cheap, float gate_px,
+                                                       float tile_frac, int tw, int tiles_x,
+                                                       int n_tiles, int2* __restrict__ items,
+                                                       int* __restrict__ n_items, SurFallbackJob job,
+                                                       SurFallbackJob* __restrict__ job_out)
+{
+    __shared__ int s_n, s_base;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *job_out = job;
+    if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    if (threadIdx.x == 0 && s_c) atomicAdd(count, s_c);
+    const int t = blockIdx.x * 16 + (threadIdx.x >> 4), sub = threadIdx.x & 15;
+    int cnt = 0, npx = 0;
+    if (t < n_tiles) {
+        const int tx = t % tiles_x, ty = t / tiles_x;
+        for (int i = sub; i < tw * 8; i += 16) {
+            const int x = tx * tw + i % tw, y = ty * 8 + i / tw;
+            if (x < W && y < H) {
+                const size_t o = (size_t)y * W + x;
+                ++npx;
+                cnt += fabsf(pred[o] - cheap[o]) > gate_px ? 1 : 0;
+            }
+        }
+    }
+    for (int off = 8; off > 0; off >>= 1) {  // within the 16 lanes of the tile
+        cnt += __shfl_xor(cnt, off);
+        npx += __shfl_xor(npx, off);
+    }
+    const bool listed = t < n_tiles && sub == 0 && (float)cnt > tile_frac * (float)npx;
+    const int slot = listed ? atomicAdd(&s_n, 1) : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = s_n ? atomicAdd(n_items, s_n) : 0;
+    __syncthreads();
+    if (listed) items[s_base + slot] = make_int2(0, t);
 }
 
 inline dim3 pix_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
@@ -551,8 +751,33 @@ hipError_t sur_gate(int n, const float* pred, const float* cheap, float gate_px,
                     hipStream_t s)
 {
     hipLaunchKernelGGL(k_sur_zero, dim3(1), dim3(1), 0, s, count);
-    hipLaunchKernelGGL(k_sur_gate, dim3((n + 255) / 256), dim3(256), 0, s, n, pred, cheap, gate_px,
-                       count);
+    hipLaunchKernelGGL(k_sur_gate, dim3(std::max(1, std::min((n + 255) / 256, 512))), dim3(256), 0, s,
+                       n, pred, cheap, gate_px, count);
+    return hipGetLastError();
+}
+
+size_t sur_net_lds_bytes()
+{
+    return (size_t)(kPlaneA + kPlaneB) * kC * sizeof(uint16_t) + 9 * kC * sizeof(float);
+}
+
+hipError_t sur_net_fwd(int W, int H, const uint16_t* feat, const uint16_t* fwd, const float* bias,
+                       const float* w3, const float* b3, const float* cheap, float* pred,
+                       int* zero2, hipStream_t s)
+{
+    dim3 grid((W + NT - 1) / NT, (H + NT - 1) / NT);
+    hipLaunchKernelGGL(k_sur_net_fwd, grid, dim3(kNetThreads), sur_net_lds_bytes(), s, W, H, feat,
+                       fwd, bias, w3, b3, cheap, pred, zero2);
+    return hipGetLastError();
+}
+
+hipError_t sur_tile_gate(int W, int H, const float* pred, const float* cheap, float gate_px,
+                         float tile_frac, int tw, int2* items, int* n_items,
+                         const SurFallbackJob& job, SurFallbackJob* job_out, hipStream_t s)
+{
+    const int tiles_x = (W + tw - 1) / tw, n_tiles = tiles_x * ((H + 7) / 8);
+    hipLaunchKernelGGL(k_sur_tile_gate, dim3((n_tiles + 15) / 16), dim3(256), 0, s, W, H, pred, cheap,
+                       gate_px, tile_frac, tw, tiles_x, n_tiles, items, n_items, job, job_out);
     return hipGetLastError();
 }
 

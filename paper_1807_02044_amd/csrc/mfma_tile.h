@@ -726,11 +726,14 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __r
                                                             const uint8_t* const* __restrict__ Rs,
                                                             int32_t* const* __restrict__ disps,
                                                             float* const* __restrict__ subs,
-                                                            Tables tb)
+                                                            Tables tb,
+                                                            const int* __restrict__ n_dev)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_next[2];
     constexpr int kThreads = 64 * NW;
+    // a queue whose length a previous kernel wrote on the device
+    if (n_dev) n_items = __builtin_amdgcn_readfirstlane(*n_dev);
     load_tables(tb, R, smem, kThreads);   // the class shares its weight tables
     if (threadIdx.x == 0) s_next[0] = atomicAdd(counter, 1);
     int buf = 0;
@@ -872,7 +875,7 @@ hipError_t launch_batch_co(const BatchClass& bc, hipStream_t s)
     }
     hipLaunchKernelGGL((k_fbs_mfma_batch<R, CH, NW, CO>), dim3(bc.grid), dim3(64 * NW), bc.lds, s,
                        bc.pairs, bc.items, bc.n_items, bc.counter, bc.L, bc.R, bc.disp, bc.sub,
-                       bc.tb);
+                       bc.tb, bc.n_dev);
     return hipGetLastError();
 }
 

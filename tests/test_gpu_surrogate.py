@@ -334,3 +334,107 @@ def test_trained_net_gains_over_cheap_run():
     assert np.mean(ev["bad1_net"]) < np.mean(ev["bad1_cheap"])
     assert np.mean(ev["mae_net"]) < np.mean(ev["mae_cheap"])
     sur.close()
+
+
+# ------------------------------------------- fused inference, tile gate
+
+def _random_net(seed):
+    rng = np.random.default_rng(seed)
+    p = {k: v.astype(np.float64) for k, v in S.init_params(seed).items()}
+    for l in range(4):
+        p[f"b{l}"] = rng.normal(0, 0.05, p[f"b{l}"].shape)
+    return pack({k: v.astype(np.float32) for k, v in p.items()})
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (5, 3), (26, 26), (27, 53), (97, 61), (640, 480)])
+def test_fused_forward_equals_layer_by_layer(W, H):
+    """fbs_surrogate_forward (one fused kernel) gives the bits of the
+    per-layer kernels that fbs_surrogate_gradients runs, at ragged sizes."""
+    _say("fused forward", W, H)
+    rng = np.random.default_rng(W * 1000 + H)
+    sur = L.FbsSurrogate(W, H, 16)
+    sur.set_params(_random_net(W + H))
+    f = np.zeros((H, W, 32), dtype=np.uint16)
+    f[..., :17] = bf16_bits(S.bf16(rng.uniform(0, 1, size=(H, W, 17))))
+    ft = torch.from_numpy(f.view(np.int16)).to(DEV)
+    cheap = dev_f32(rng.uniform(0, 60, size=(H, W)))
+    label = dev_f32(rng.uniform(0, 60, size=(H, W)))
+    fused = torch.full((H, W), -1.0, dtype=torch.float32, device=DEV)
+    layered = torch.full((H, W), -2.0, dtype=torch.float32, device=DEV)
+    g = torch.empty(sur.n_params, dtype=torch.float32, device=DEV)
+    sur.forward(W, H, ft, cheap, fused)
+    sur.gradients(W, H, ft, cheap, label, layered, g)
+    torch.cuda.synchronize()
+    a, b = fused.cpu().numpy(), layered.cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), np.argwhere(a != b)[:5]
+    assert np.abs(a - cheap.cpu().numpy()).max() > 0  # the net did something
+    sur.close()
+
+
+def _tile_rule(pred, cheap, gate_px, tile_frac, tw):
+    """Host restatement of the tile gate: tile -> listed?"""
+    H, W = pred.shape
+    bad = np.abs(pred - cheap) > gate_px
+    out = {}
+    for ty in range((H + 7) // 8):
+        for tx in range((W + tw - 1) // tw):
+            blk = bad[8 * ty:8 * ty + 8, tw * tx:tw * tx + tw]
+            out[(ty, tx)] = float(blk.sum()) > tile_frac * float(blk.size)
+    return out
+
+
+@pytest.mark.parametrize("W,H,D", [(96, 64, 24), (131, 45, 40)])
+def test_run_tiled(W, H, D):
+    """Tile-gated run: every tile holds either the net's prediction or,
+    where the gate lists it, exactly the full run's values."""
+    _say("run_tiled", W, H, D)
+    wl, pr, cheap, full = _pair(W, H, D)
+    assert L.fbs_validate(full) == 0 and L.fbs_validate(cheap) == 0
+    Lt, Rt = torch.from_numpy(pr.left).to(DEV), torch.from_numpy(pr.right).to(DEV)
+    sur = L.FbsSurrogate(W, H, D)
+    sur.set_params(pack(S.init_params(3)))
+    csub = torch.empty((H, W), dtype=torch.float32, device=DEV)
+    feat = torch.empty((H, W, 32), dtype=torch.int16, device=DEV)
+    pred = torch.empty((H, W), dtype=torch.float32, device=DEV)
+    sur.cheap_run(cheap, Lt, Rt, csub, feat)
+    sur.forward(W, H, feat, csub, pred)
+    _, full_sub = fbs.run(full, Lt, Rt)
+    out = torch.full((H, W), -7.0, dtype=torch.float32, device=DEV)
+    sur.run_tiled(cheap, full, Lt, Rt, out, 1.0, 1.0)    # no tile listed
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), pred.cpu().numpy())
+    sur.run_tiled(cheap, full, Lt, Rt, out, 1.0, -1.0)   # every tile listed
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), full_sub.cpu().numpy())
+    # a gate that lists some tiles: check each tile against the rule
+    _, nw, _ = L.FbsPlan([full]).pair_config(0)
+    p_, c_ = pred.cpu().numpy(), csub.cpu().numpy()
+    tw = 2 * nw
+    gate = float(np.median(np.abs(p_ - c_)))   # about half the pixels disagree
+    bad = np.abs(p_ - c_) > gate
+    fr = sorted({float(bad[8 * ty:8 * ty + 8, tw * tx:tw * tx + tw].mean())
+                 for ty in range((H + 7) // 8) for tx in range((W + tw - 1) // tw)})
+    k = len(fr) // 2
+    assert len(fr) >= 2
+    frac = 0.5 * (fr[max(k - 1, 0)] + fr[k])   # between two tile fractions: no ties
+    rule = _tile_rule(p_, c_, gate, frac, tw)
+    n_listed = sum(rule.values())
+    _say("tiles", len(rule), "listed", n_listed, "nw", nw)
+    assert 0 < n_listed < len(rule)
+    out.fill_(-7.0)
+    sur.run_tiled(cheap, full, Lt, Rt, out, gate, frac)
+    torch.cuda.synchronize()
+    o, fs = out.cpu().numpy(), full_sub.cpu().numpy()
+    for (ty, tx), listed in rule.items():
+        sl = (slice(8 * ty, 8 * ty + 8), slice(tw * tx, tw * tx + tw))
+        np.testing.assert_array_equal(o[sl], (fs if listed else p_)[sl], err_msg=str((ty, tx, listed)))
+    # reruns of the same call are identical (the device list is rebuilt each time)
+    o2 = torch.full((H, W), -7.0, dtype=torch.float32, device=DEV)
+    sur.run_tiled(cheap, full, Lt, Rt, o2, gate, frac)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(o2.cpu().numpy(), o)
+    # a full run that forces the vector ALUs is rejected
+    with pytest.raises(L.FbsError):
+        v = fbs.params_for(wl.with_(radius=6, sigma_s=6.0), flags=L.FBS_F_FORCE_VALU)
+        sur.run_tiled(cheap, v, Lt, Rt, out, 1.0, 0.1)
+    sur.close()
