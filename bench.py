@@ -244,6 +244,24 @@ def surrogate(args, dev):
         res[f"gate_{name}"] = {"gate_px": 1.0, "gate_frac": frac, "frames_per_s": 1.0 / t,
                                "fallback_rate": rate, "bad1_vs_plain": b,
                                "speedup_vs_plain": t_plain / t}
+    # per-tile fallback (fbs_surrogate_run_tiled), gate calibrated on training pairs
+    tg = summary.get("gate_tiles")
+    if tg:
+        gpx, tfrac = float(tg["gate_px"]), float(tg["tile_frac"])
+        t = timed(lambda i: sur.run_tiled(pc, pf, Ls[i], Rs[i], out, gpx, tfrac, stream))
+        tb, teq = [], []
+        with torch.cuda.stream(stream):
+            for i in range(n):
+                sur.run_tiled(pc, pf, Ls[i], Rs[i], out, gpx, tfrac, stream)
+                tb.append(float(((out - plain[i]).abs() > 1.0).float().mean().item()))
+                teq.append(float((out == plain[i]).float().mean().item()))
+        res["gate_tiles"] = {"gate_px": gpx, "tile_frac": tfrac, "frames_per_s": 1.0 / t,
+                             "bad1_vs_plain": float(np.mean(tb)),
+                             "bad1_vs_plain_max": float(np.max(tb)),
+                             "pixels_equal_to_plain": float(np.mean(teq)),
+                             "speedup_vs_plain": t_plain / t,
+                             "calibration": {k: tg[k] for k in ("train_frames", "target_bad1",
+                                                                "train_bad1_p90")}}
     sur.close()
     return res
 

@@ -10,17 +10,19 @@ hipError_t launch_mfma_features(const Geom& g, const Tables& t, const uint8_t* L
     float scap;
     if (g.C != 1 || g.D < 8 || !mfma_supported(g) || !scaled_cap(g, &scap) || !feat)
         return hipErrorInvalidValue;
-    // 8 waves; slab depth as for fbs_run (cached per radius and disparity blocks)
+    // 8 or 12 waves and the slab depth picked as for fbs_run (most resident
+    // waves), cached per radius and disparity blocks
     static std::atomic<int> cache[kMaxR + 1][FBS_MAX_DISP / 16 + 1];
     const int nblk = (g.D + 15) >> 4;
-    int nb = cache[g.r][nblk].load(std::memory_order_relaxed);
-    if (nb == 0) {
-        static const int cands[1] = {8};
+    int packed = cache[g.r][nblk].load(std::memory_order_relaxed);
+    if (packed == 0) {
+        static const int cands[2] = {8, 12};
         MfmaCfg c{8, 1};
-        nb = pick_cfg<FeatOccupancyAny>(g, cands, 1, &c) ? c.nb : 1;
-        cache[g.r][nblk].store(nb, std::memory_order_relaxed);
+        packed = pick_cfg<FeatOccupancyAny>(g, cands, 2, &c) ? (c.nw << 8) | c.nb : (8 << 8) | 1;
+        cache[g.r][nblk].store(packed, std::memory_order_relaxed);
     }
-    const TileJob job{g, scap, nb, L, R, nullptr, sub, nullptr, feat};
+    const TileJob job{g, scap, packed & 255, L, R, nullptr, sub, nullptr, feat};
+    if ((packed >> 8) == 12) return dispatch_r<FeatLauncher, 1, 12>(g.r, job, t, s);
     return dispatch_r<FeatLauncher, 1, 8>(g.r, job, t, s);
 }
 

@@ -27,6 +27,7 @@ namespace fbs {
 namespace {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int kC = SUR_CH;  // padded channels
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // float -> bfloat16 bits, round to nearest even (no NaN inputs here)
@@ -37,8 +38,24 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+// two floats -> packed bfloat16 (a in the low half), round to nearest even:
+// one v_cvt_pk_bf16_f32, the same bits as to_bf16 on each
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v{a, b}), bf2));
+}
+// A operand of the 32 -> 1 layer for one tap: output row 0 holds the weights
+// of the 32 input channels (BF16-exact floats), rows 1..15 are zero
+__device__ __forceinline__ bf8 last_layer_a(const float* __restrict__ w3, int tap, int m, int kq)
+{
+    bf8 a;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = (__bf16)(m == 0 ? w3[tap * kC + 8 * kq + i] : 0.0f);
+    return a;
+}
 
-constexpr int kC = SUR_CH;  // padded channels
 
 // ---------------------------------------------------------------- features
 
@@ -139,32 +156,39 @@ __global__ __launch_bounds__(256) void k_sur_conv(int W, int H, const uint16_t* 
         const int ty = grp >> 1, tx0 = (grp & 1) * 16;
         const int y = Y0 + ty;
         const int x = X0 + tx0 + m;  // this lane's pixel (B operand column / result column)
+        f4 acc2[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {  // one B operand serves both output blocks
+            const int ky = t / 3, kx = t - 3 * (t / 3);
+            const bf8 b = *reinterpret_cast<const bf8*>(
+                s_in + ((ty + ky) * (CT_W + 2) + (tx0 + m + kx)) * kC + 8 * kq);
+            acc2[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[t][0], b, acc2[0], 0, 0, 0);
+            acc2[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[t][1], b, acc2[1], 0, 0, 0);
+        }
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int ky = t / 3, kx = t - 3 * (t / 3);
-                const bf8 b = *reinterpret_cast<const bf8*>(
-                    s_in + ((ty + ky) * (CT_W + 2) + (tx0 + m + kx)) * kC + 8 * kq);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[t][cb], b, acc, 0, 0, 0);
-            }
+            const f4& acc = acc2[cb];
             if (x < W && y < H) {
                 const int c0 = cb * 16 + 4 * kq;
                 const size_t o = ((size_t)y * W + x) * kC + c0;
-                uint16_t r[4];
+                uint2 v;
                 if (MODE == SUR_FWD) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) r[j] = to_bf16(fmaxf(acc[j] + bias[c0 + j], 0.0f));
+                    v.x = pack_bf16(fmaxf(acc[0] + bias[c0], 0.0f), fmaxf(acc[1] + bias[c0 + 1], 0.0f));
+                    v.y = pack_bf16(fmaxf(acc[2] + bias[c0 + 2], 0.0f), fmaxf(acc[3] + bias[c0 + 3], 0.0f));
                 } else {
+                    // keep the gradient where the forward activation is > 0
                     const uint2 mk = *reinterpret_cast<const uint2*>(mask_act + o);
-                    const uint16_t mv[4] = {(uint16_t)(mk.x & 0xffff), (uint16_t)(mk.x >> 16),
-                                            (uint16_t)(mk.y & 0xffff), (uint16_t)(mk.y >> 16)};
+                    const uint32_t mw[2] = {mk.x, mk.y};
+                    uint32_t r[2];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) r[j] = from_bf16(mv[j]) > 0.0f ? to_bf16(acc[j]) : 0;
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t keep = (from_bf16((uint16_t)(mw[h] & 0xffff)) > 0.0f ? 0xffffu : 0u) |
+                                              (from_bf16((uint16_t)(mw[h] >> 16)) > 0.0f ? 0xffff0000u : 0u);
+                        r[h] = pack_bf16(acc[2 * h], acc[2 * h + 1]) & keep;
+                    }
+                    v = make_uint2(r[0], r[1]);
                 }
-                *reinterpret_cast<uint2*>(out + o) =
-                    make_uint2((uint32_t)r[0] | ((uint32_t)r[1] << 16), (uint32_t)r[2] | ((uint32_t)r[3] << 16));
+                *reinterpret_cast<uint2*>(out + o) = v;
             }
         }
     }
@@ -172,32 +196,64 @@ __global__ __launch_bounds__(256) void k_sur_conv(int W, int H, const uint16_t* 
 
 // ------------------------------------------------ fused inference (whole net)
 //
-// One workgroup: an NT x NT tile of predictions.  The tile's features plus a
-// 4-pixel halo (the receptive radius of four 3x3 layers) are staged in LDS;
-// each 32 -> 32 layer reads one LDS buffer and writes the other, its square
-// shrinking by one pixel per side (34 -> 32 -> 30 -> 28), and the 32 -> 1
-// layer reads the last one.  Activations of positions off the image are
-// stored as 0: every layer sees the zero padding of a 'same' convolution.
+// One workgroup (4 waves) per NT x NT tile of predictions.  The tile's
+// features plus a 4-pixel halo (the receptive radius of four 3x3 layers) are
+// staged in one LDS buffer, and each layer overwrites it in place: a layer's
+// output square is one pixel smaller per side (34 -> 32 -> 30 -> 28 -> 26)
+// and output (r, c) only reads inputs (r..r+2, c..c+2), so every wave keeps
+// its results in registers until all waves have read their inputs, then
+// stores them at (r, c).  Activations of positions off the image are stored
+// as 0: every layer sees the zero padding of a 'same' convolution.  At 75 KB
+// of LDS two workgroups share a compute unit, one staging while the other
+// computes.
 //
-// LDS holds activations by channel octet: plane q keeps channels 8q..8q+7 of
-// every pixel in 16 bytes, so the 16 pixels of an MFMA B operand are 256
-// contiguous bytes (no bank conflicts).  A wave takes 16 columns x 4 rows of a
-// layer's output; each B operand (input row, column shift) it loads serves the
-// (up to) three output rows that use it.  Every output is summed in the same
-// order as in k_sur_conv / k_sur_last_fwd, so the predictions are
-// bit-identical to the per-layer kernels'.
+// The buffer holds activations by channel octet: plane q keeps channels
+// 8q..8q+7 of every pixel in 16 bytes, so the 16 pixels of an MFMA B operand
+// are 256 contiguous bytes (no bank conflicts).  A wave item is 16 columns x
+// 4 rows of a layer's output; each B operand (input row, column shift) it
+// loads serves the (up to) three output rows that use it.  Every output is
+// summed in the same order as in k_sur_conv / k_sur_last_fwd, so the
+// predictions are bit-identical to the per-layer kernels'.
 constexpr int NT = 26, NS0 = NT + 8;
-constexpr int kNetThreads = 512;
-constexpr int kPlaneA = NS0 * NS0, kPlaneB = (NS0 - 2) * (NS0 - 2);
+constexpr int kNetThreads = 256, kNetWaves = kNetThreads / 64;
+constexpr int kPlane = NS0 * NS0;  // pixels per channel-octet plane, pitch NS0
 
+// The MFMA sums of one item: output rows r0..r0+3 (those below so), columns
+// 16 seg .. 16 seg + 15 of a layer whose input square has side si.
+template <int NCB>
+__device__ __forceinline__ void net_item(const uint16_t* __restrict__ plane, const bf8 (&aw)[9][NCB],
+                                         int si, int so, int r0, int c, f4 (&acc)[4][NCB])
+{
+#pragma unroll
+    for (int qi = 0; qi < 6; ++qi) {
+        const int q = r0 + qi;  // input row
+        if (q >= si) break;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            // columns past the output are computed from clamped reads and dropped
+            const int col = min(c + kx, si - 1);
+            const bf8 b = *reinterpret_cast<const bf8*>(plane + (size_t)(q * NS0 + col) * 8);
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky) {
+                const int r = qi - ky;  // output row r0 + r takes input row q as tap row ky
+                if (r >= 0 && r < 4 && r0 + r < so) {
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb)
+                        acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[3 * ky + kx][cb], b, acc[r][cb], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
+// One 32 -> 32 layer, input side SI, in place.
 template <int SI>
-__device__ __forceinline__ void net_layer(const uint16_t* __restrict__ src, int srcP,
-                                          uint16_t* __restrict__ dst, int dstP,
-                                          const uint16_t* __restrict__ A,
+__device__ __forceinline__ void net_layer(uint16_t* __restrict__ buf, const uint16_t* __restrict__ A,
                                           const float* __restrict__ bias, int W, int H, int oy,
                                           int ox, int lane, int wave)
 {
     constexpr int SO = SI - 2, NSEG = (SO + 15) / 16, NSTRIP = (SO + 3) / 4;
+    constexpr int NITEM = NSEG * NSTRIP, PER = (NITEM + kNetWaves - 1) / kNetWaves;
     const int m = lane & 15, kq = lane >> 4;
     bf8 aw[9][2];
 #pragma unroll
@@ -210,51 +266,55 @@ __device__ __forceinline__ void net_layer(const uint16_t* __restrict__ src, int 
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) bs[cb][j] = bias[cb * 16 + 4 * kq + j];
-    const uint16_t* plane = src + (size_t)kq * srcP * 8;
-#pragma unroll 1
-    for (int item = wave; item < NSEG * NSTRIP; item += kNetThreads / 64) {
-        const int seg = item % NSEG, r0 = (item / NSEG) * 4;
-        const int c = seg * 16 + m;  // output column of this lane (B / result column)
-        f4 acc[4][2];
+    const uint16_t* plane = buf + (size_t)kq * kPlane * 8;
+    uint2 res[PER][4][2];  // packed BF16 results, stored after the barrier
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < PER; ++k) {
+        const int item = wave + kNetWaves * k;
+        if (item < NITEM) {
+            const int seg = item % NSEG, r0 = (item / NSEG) * 4;
+            const int c = seg * 16 + m;
+            f4 acc[4][2];
 #pragma unroll
-        for (int qi = 0; qi < 6; ++qi) {
-            const int q = r0 + qi;  // input row
-            if (q >= SI) break;
-#pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                // columns past the output are computed from clamped reads and dropped
-                const int col = min(c + kx, SI - 1);
-                const bf8 b = *reinterpret_cast<const bf8*>(plane + (size_t)(q * SI + col) * 8);
-#pragma unroll
-                for (int ky = 0; ky < 3; ++ky) {
-                    const int r = qi - ky;  // output row r0 + r takes input row q as tap row ky
-                    if (r >= 0 && r < 4 && r0 + r < SO) {
-                        acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[3 * ky + kx][0], b, acc[r][0], 0, 0, 0);
-                        acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[3 * ky + kx][1], b, acc[r][1], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        if (c < SO) {
+            for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = f4{0.f, 0.f, 0.f, 0.f};
+            net_item<2>(plane, aw, SI, SO, r0, c, acc);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                if (r0 + r >= SO) break;
                 const int y = oy + r0 + r, x = ox + c;
-                const bool in = x >= 0 && x < W && y >= 0 && y < H;
+                const uint32_t keep = (x >= 0 && x < W && y >= 0 && y < H) ? 0xffffffffu : 0u;
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
-                    const int c0 = cb * 16 + 4 * kq;
-                    uint16_t v[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) v[j] = in ? to_bf16(fmaxf(acc[r][cb][j] + bs[cb][j], 0.0f)) : 0;
-                    *reinterpret_cast<uint2*>(dst + ((size_t)(c0 >> 3) * dstP + (r0 + r) * SO + c) * 8 + (c0 & 7)) =
-                        make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16));
+                    const f4& a = acc[r][cb];
+                    res[k][r][cb] = make_uint2(
+                        pack_bf16(fmaxf(a[0] + bs[cb][0], 0.0f), fmaxf(a[1] + bs[cb][1], 0.0f)) & keep,
+                        pack_bf16(fmaxf(a[2] + bs[cb][2], 0.0f), fmaxf(a[3] + bs[cb][3], 0.0f)) & keep);
                 }
             }
         }
     }
+    __syncthreads();  // every wave has read this layer's input
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int item = wave + kNetWaves * k;
+        if (item < NITEM) {
+            const int seg = item % NSEG, r0 = (item / NSEG) * 4;
+            const int c = seg * 16 + m;
+            if (c < SO) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r0 + r < SO) {
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb) {
+                            const int c0 = cb * 16 + 4 * kq;
+                            *reinterpret_cast<uint2*>(buf + ((size_t)(c0 >> 3) * kPlane + (r0 + r) * NS0 + c) * 8 +
+                                                      (c0 & 7)) = res[k][r][cb];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(kNetThreads) void k_sur_net_fwd(int W, int H, const uint16_t* __restrict__ feat,
@@ -267,64 +327,64 @@ __global__ __launch_bounds__(kNetThreads) void k_sur_net_fwd(int W, int H, const
                                                              int* __restrict__ zero2)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint16_t* bufA = reinterpret_cast<uint16_t*>(smem);
-    uint16_t* bufB = bufA + (size_t)kPlaneA * kC;
-    float* s_w3 = reinterpret_cast<float*>(bufB + (size_t)kPlaneB * kC);
+    uint16_t* buf = reinterpret_cast<uint16_t*>(smem);
+    float* s_w3 = reinterpret_cast<float*>(buf + (size_t)kPlane * kC);
     const int tid = threadIdx.x, lane = tid & 63;
-    for (int i = tid; i < 9 * kC; i += kNetThreads) s_w3[i] = w3[i];
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (zero2 && blockIdx.x == 0 && blockIdx.y == 0 && tid < 2) zero2[tid] = 0;
-    const int X0 = blockIdx.x * NT - 4, Y0 = blockIdx.y * NT - 4;  // image position of bufA's origin
-    for (int i = tid; i < kPlaneA * 4; i += kNetThreads) {
+    for (int i = tid; i < 9 * kC; i += kNetThreads) s_w3[i] = w3[i];
+    const int X0 = blockIdx.x * NT - 4, Y0 = blockIdx.y * NT - 4;  // image position of the buffer's origin
+    for (int i = tid; i < kPlane * 4; i += kNetThreads) {
         const int px = i >> 2, q = i & 3;
         const int ty = px / NS0, tx = px - ty * NS0;
         const int y = Y0 + ty, x = X0 + tx;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (x >= 0 && x < W && y >= 0 && y < H)
             v = reinterpret_cast<const uint4*>(feat + ((size_t)y * W + x) * kC)[q];
-        reinterpret_cast<uint4*>(bufA)[(size_t)q * kPlaneA + px] = v;
+        reinterpret_cast<uint4*>(buf)[(size_t)q * kPlane + px] = v;
     }
     __syncthreads();
     constexpr int LW = 9 * kC * kC;
-    net_layer<NS0>(bufA, kPlaneA, bufB, kPlaneB, fwd, bias, W, H, Y0 + 1, X0 + 1, lane, wave);
-    __syncthreads();
-    net_layer<NS0 - 2>(bufB, kPlaneB, bufA, kPlaneA, fwd + LW, bias + kC, W, H, Y0 + 2, X0 + 2, lane, wave);
-    __syncthreads();
-    net_layer<NS0 - 4>(bufA, kPlaneA, bufB, kPlaneB, fwd + 2 * LW, bias + 2 * kC, W, H, Y0 + 3, X0 + 3, lane, wave);
-    __syncthreads();
-    // 32 -> 1 layer and the residual; bufB holds layer 3 on a 28-pixel square
-    constexpr int S3 = NS0 - 6;
-    for (int i = tid; i < NT * NT; i += kNetThreads) {
-        const int r = i / NT, c = i - r * NT;
-        const int y = Y0 + 4 + r, x = X0 + 4 + c;
-        if (x >= W || y >= H) continue;
-        float acc = *b3;
-        for (int t = 0; t < 9; ++t) {
-            const int ky = t / 3, kx = t - 3 * ky;
-            const int yy = y + ky - 1, xx = x + kx - 1;
-            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-            const int px = (r + ky) * S3 + (c + kx);
+    net_layer<NS0>(buf, fwd, bias, W, H, Y0 + 1, X0 + 1, lane, wave);
+    net_layer<NS0 - 2>(buf, fwd + LW, bias + kC, W, H, Y0 + 2, X0 + 2, lane, wave);
+    net_layer<NS0 - 4>(buf, fwd + 2 * LW, bias + 2 * kC, W, H, Y0 + 3, X0 + 3, lane, wave);
+    // 32 -> 1 layer and the residual: the same MFMA scheme with only output
+    // row 0 weighted, started from the bias (the sums of k_sur_last_fwd, in
+    // its order)
+    constexpr int SI = NS0 - 6, SO = NT, NSEG = (SO + 15) / 16, NSTRIP = (SO + 3) / 4;
+    const int m = lane & 15, kq = lane >> 4;
+    bf8 aw[9][1];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint4 v = reinterpret_cast<const uint4*>(bufB)[(size_t)q * kPlaneB + px];
-                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+    for (int t = 0; t < 9; ++t) aw[t][0] = last_layer_a(s_w3, t, m, kq);
+    const float bias3 = *b3;
+    const uint16_t* plane = buf + (size_t)kq * kPlane * 8;
+#pragma unroll 1
+    for (int item = wave; item < NSEG * NSTRIP; item += kNetWaves) {
+        const int seg = item % NSEG, r0 = (item / NSEG) * 4;
+        const int c = seg * 16 + m;
+        f4 acc[4][1];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int ch = 8 * q + 2 * e;
-                    acc = fmaf(s_w3[t * kC + ch], from_bf16((uint16_t)(u[e] & 0xffff)), acc);
-                    acc = fmaf(s_w3[t * kC + ch + 1], from_bf16((uint16_t)(u[e] >> 16)), acc);
+        for (int r = 0; r < 4; ++r) acc[r][0] = f4{lane < 16 ? bias3 : 0.0f, 0.f, 0.f, 0.f};
+        net_item<1>(plane, aw, SI, SO, r0, c, acc);
+        if (lane < 16 && c < SO) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int y = Y0 + 4 + r0 + r, x = X0 + 4 + c;
+                if (r0 + r < SO && x < W && y < H) {
+                    const size_t o = (size_t)y * W + x;
+                    pred[o] = cheap[o] + acc[r][0][0];
                 }
             }
         }
-        const size_t o = (size_t)y * W + x;
-        pred[o] = cheap[o] + acc;
     }
 }
 
 // ------------------------------------------------------------- last layer
 
-// resid[p] = sum_{tap, c} W3[tap][c] a3[p + off][c] + b3; pred = cheap + resid;
-// with a label: g4 = bf16(sign(pred - label) / N) and per-block |pred - label| sums.
+// resid[p] = b3 + sum_{tap, c} W3[tap][c] a3[p + off][c]; pred = cheap + resid;
+// with a label: g4 = bf16(sign(pred - label) / N) and per-tile |pred - label|
+// sums.  Tiles and MFMA scheme of k_sur_conv with one weighted output row,
+// the accumulator started from the bias.
 __global__ __launch_bounds__(256) void k_sur_last_fwd(int W, int H, const uint16_t* __restrict__ a3,
                                                       const float* __restrict__ w3,
                                                       const float* __restrict__ b3,
@@ -334,49 +394,58 @@ __global__ __launch_bounds__(256) void k_sur_last_fwd(int W, int H, const uint16
                                                       float* __restrict__ g4,
                                                       float* __restrict__ loss_part)
 {
-    __shared__ float s_w[9 * kC];
-    __shared__ float s_red[256];
-    for (int i = threadIdx.x; i < 9 * kC; i += 256) s_w[i] = w3[i];
+    __shared__ __align__(16) uint16_t s_in[(CT_H + 2) * (CT_W + 2) * kC];
+    __shared__ float s_red[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int X0 = blockIdx.x * CT_W, Y0 = blockIdx.y * CT_H;
+    constexpr int kChunks = (CT_H + 2) * (CT_W + 2) * (kC / 8);
+    for (int i = tid; i < kChunks; i += 256) {
+        const int px = i / (kC / 8), c8 = i - px * (kC / 8);
+        const int ty = px / (CT_W + 2), tx = px - ty * (CT_W + 2);
+        const int y = Y0 - 1 + ty, x = X0 - 1 + tx;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (x >= 0 && x < W && y >= 0 && y < H)
+            v = reinterpret_cast<const uint4*>(a3 + ((size_t)y * W + x) * kC)[c8];
+        reinterpret_cast<uint4*>(s_in)[i] = v;
+    }
+    const int m = lane & 15, kq = lane >> 4;
+    bf8 aw[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) aw[t] = last_layer_a(w3, t, m, kq);
+    const float bias3 = *b3;
     __syncthreads();
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     float err = 0.0f;
-    if (x < W && y < H) {
-        float acc = *b3;
+#pragma unroll 1
+    for (int gi = 0; gi < 4; ++gi) {
+        const int grp = wave * 4 + gi;
+        const int ty = grp >> 1, tx0 = (grp & 1) * 16;
+        const int y = Y0 + ty, x = X0 + tx0 + m;
+        f4 acc = {lane < 16 ? bias3 : 0.0f, 0.f, 0.f, 0.f};
+#pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-            const uint4* src = reinterpret_cast<const uint4*>(a3 + ((size_t)yy * W + xx) * kC);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint4 v = src[q];
-                const uint32_t u[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int c = 8 * q + 2 * e;
-                    acc = fmaf(s_w[t * kC + c], from_bf16((uint16_t)(u[e] & 0xffff)), acc);
-                    acc = fmaf(s_w[t * kC + c + 1], from_bf16((uint16_t)(u[e] >> 16)), acc);
-                }
-            }
+            const int ky = t / 3, kx = t - 3 * (t / 3);
+            const bf8 b = *reinterpret_cast<const bf8*>(
+                s_in + ((ty + ky) * (CT_W + 2) + (tx0 + m + kx)) * kC + 8 * kq);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[t], b, acc, 0, 0, 0);
         }
-        const size_t o = (size_t)y * W + x;
-        const float pv = cheap[o] + acc;
-        pred[o] = pv;
-        if (label) {
-            const float d = pv - label[o];
-            err = fabsf(d);
-            const float s = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-            g4[o] = from_bf16(to_bf16(s / (float)((size_t)W * H)));
+        if (lane < 16 && x < W && y < H) {
+            const size_t o = (size_t)y * W + x;
+            const float pv = cheap[o] + acc[0];
+            pred[o] = pv;
+            if (label) {
+                const float d = pv - label[o];
+                err += fabsf(d);
+                const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
+                g4[o] = from_bf16(to_bf16(sg / (float)((size_t)W * H)));
+            }
         }
     }
     if (label) {
-        s_red[threadIdx.x] = err;
+        // fixed-order sum: lanes of a wave, then the four waves
+        for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
+        if (lane == 0) s_red[wave] = err;
         __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) s_red[threadIdx.x] += s_red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) loss_part[blockIdx.y * gridDim.x + blockIdx.x] = s_red[0];
+        if (tid == 0) loss_part[blockIdx.y * gridDim.x + blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
     }
 }
 
@@ -685,12 +754,13 @@ hipError_t sur_last_fwd(int W, int H, const uint16_t* a3, const float* w3, const
                         const float* cheap, float* pred, const float* label, float* g4,
                         float* loss_part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sur_last_fwd, pix_grid(W, H), dim3(256), 0, s, W, H, a3, w3, b3, cheap,
-                       pred, label, g4, loss_part);
+    dim3 grid((W + CT_W - 1) / CT_W, (H + CT_H - 1) / CT_H);
+    hipLaunchKernelGGL(k_sur_last_fwd, grid, dim3(256), 0, s, W, H, a3, w3, b3, cheap, pred,
+                       label, g4, loss_part);
     return hipGetLastError();
 }
 
-int sur_loss_parts(int W, int H) { return ((W + 63) / 64) * ((H + 3) / 4); }
+int sur_loss_parts(int W, int H) { return ((W + CT_W - 1) / CT_W) * ((H + CT_H - 1) / CT_H); }
 
 hipError_t sur_last_bwd(int W, int H, const float* g4, const float* w3, const uint16_t* a3,
                         uint16_t* gz, hipStream_t s)
@@ -756,10 +826,7 @@ hipError_t sur_gate(int n, const float* pred, const float* cheap, float gate_px,
     return hipGetLastError();
 }
 
-size_t sur_net_lds_bytes()
-{
-    return (size_t)(kPlaneA + kPlaneB) * kC * sizeof(uint16_t) + 9 * kC * sizeof(float);
-}
+size_t sur_net_lds_bytes() { return (size_t)kPlane * kC * sizeof(uint16_t) + 9 * kC * sizeof(float); }
 
 hipError_t sur_net_fwd(int W, int H, const uint16_t* feat, const uint16_t* fwd, const float* bias,
                        const float* w3, const float* b3, const float* cheap, float* pred,

@@ -375,7 +375,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
 #pragma unroll
     for (int j = 0; j < 8; ++j) ones[j] = (_Float16)1.0f;
     f4 dh = {0.f, 0.f, 0.f, 0.f}, dl = {0.f, 0.f, 0.f, 0.f};
-    float den = 0.0f;
+    float rden = 0.0f;  // 1 / Eq. 6's denominator
     const float inv_scale = 1.0f / (CH == 3 ? 3.0f : 1.0f);
     if constexpr (!CO) {
         if (want_den) {
@@ -384,7 +384,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
                 dh = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, whi[c], dh, 0, 0, 0);
                 dl = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, wlo[c], dl, 0, 0, 0);
             }
-            den = dh[0] + dl[0];
+            rden = 1.0f / (dh[0] + dl[0]);
         }
     }
 
@@ -393,16 +393,19 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     float best = kInf, cm = kInf, cp = kInf, prev = kInf, first_v = kInf, last_v = kInf;
     int bi = -1;
     bool need_cp = false;
-    // FEAT: this lane's 8 lowest aggregated costs of its quarter, ascending
-    float tv[FEAT ? 8 : 1];
-    int tk[FEAT ? 8 : 1];
+    // FEAT: this lane's 8 lowest aggregated costs of its quarter, ascending,
+    // as keys (cost bits << 32 | k): costs are >= 0, so the keys order by
+    // cost and then by disparity
+    uint64_t tkey[FEAT ? 8 : 1];
     if constexpr (FEAT) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            tv[i] = kInf;
-            tk[i] = 0;
-        }
+        for (int i = 0; i < 8; ++i) tkey[i] = ~0ull;
     }
+    auto ce = [](uint64_t& a, uint64_t& b) {  // compare-exchange: a <= b after
+        const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+        a = lo;
+        b = hi;
+    };
 
     // Offset (halves) of octet 4c + gq of the group's union within a plane.
     // It is periodic in c with period P = lcm(4, OPR) / 4 chunks (P chunks
@@ -521,25 +524,34 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
                 need_cp = lt;
                 prev = v;
                 if (agg && pin)
-                    agg[(size_t)k * g.W * g.H + (size_t)py * g.W + px] = (v / den) * inv_scale;
-                if constexpr (FEAT) {
-                    // k rises within a quarter: insert after equal values
-                    const float a = (v / den) * inv_scale;
-                    if (a < tv[7]) {
-#pragma unroll
-                        for (int i = 7; i >= 0; --i) {
-                            const bool shift = i > 0 && a < tv[i > 0 ? i - 1 : 0];
-                            if (shift) {
-                                tv[i] = tv[i - 1];
-                                tk[i] = tk[i - 1];
-                            } else if (a < tv[i]) {
-                                tv[i] = a;
-                                tk[i] = k;
-                            }
-                        }
-                    }
-                }
+                    agg[(size_t)k * g.W * g.H + (size_t)py * g.W + px] = (v * rden) * inv_scale;
             }
+        }
+        if constexpr (FEAT) {
+            // the block's four keys, sorted, then merged into the running
+            // list: the lowest 8 of list and block form a bitonic sequence
+            // (list[0..3], min(list[4+i], blk[3-i])) that three
+            // compare-exchange stages sort
+            uint64_t bk[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = kb + j;
+                const float a = (k < D) ? ((acc_h[j] + acc_l[j]) * rden) * inv_scale : kInf;
+                bk[j] = k < D ? ((uint64_t)__float_as_uint(a) << 32) | (uint32_t)k : ~0ull;
+            }
+            ce(bk[0], bk[1]);
+            ce(bk[2], bk[3]);
+            ce(bk[0], bk[2]);
+            ce(bk[1], bk[3]);
+            ce(bk[1], bk[2]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) tkey[4 + i] = tkey[4 + i] < bk[3 - i] ? tkey[4 + i] : bk[3 - i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ce(tkey[i], tkey[i + 4]);
+#pragma unroll
+            for (int i : {0, 1, 4, 5}) ce(tkey[i], tkey[i + 2]);
+#pragma unroll
+            for (int i : {0, 2, 4, 6}) ce(tkey[i], tkey[i + 1]);
         }
     };
 
@@ -573,7 +585,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
             for (int b = 0; b < kCoMax; ++b)
                 if (b < nblk) al[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[b], wl, al[b], 0, 0, 0);
         }
-        if (want_den) den = dh[0] + dl[0];
+        if (want_den) rden = 1.0f / (dh[0] + dl[0]);
 #pragma unroll
         for (int b = 0; b < kCoMax; ++b)
             if (b < nblk) wta_block(gq * Q + 4 * b, ah[b], al[b]);
@@ -648,26 +660,26 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
         const float dn = (float)(D - 1);
 #pragma unroll
         for (int rnd = 0; rnd < 8; ++rnd) {
-            float bvv = __shfl(tv[0], n);
-            int bkk = __shfl(tk[0], n), bt = 0;
+            // the smallest head key of the four quarters (keys are unique)
+            uint64_t best_key = 0;
+            int bt = 0;
 #pragma unroll
-            for (int t = 1; t < 4; ++t) {
-                const float v = __shfl(tv[0], n + 16 * t);
-                const int k = __shfl(tk[0], n + 16 * t);
-                if (v < bvv) {
-                    bvv = v;
-                    bkk = k;
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t hi = __shfl((uint32_t)(tkey[0] >> 32), n + 16 * t);
+                const uint32_t lo = __shfl((uint32_t)tkey[0], n + 16 * t);
+                const uint64_t key = ((uint64_t)hi << 32) | lo;
+                if (t == 0 || key < best_key) {
+                    best_key = key;
                     bt = t;
                 }
             }
             if (gq == bt) {
 #pragma unroll
-                for (int i = 0; i < 7; ++i) {
-                    tv[i] = tv[i + 1];
-                    tk[i] = tk[i + 1];
-                }
-                tv[7] = kInf;
+                for (int i = 0; i < 7; ++i) tkey[i] = tkey[i + 1];
+                tkey[7] = ~0ull;
             }
+            const float bvv = __uint_as_float((uint32_t)(best_key >> 32));
+            const int bkk = (int)(uint32_t)best_key;
             const uint32_t cb = bf16_bits(bvv / g.tau), ib = bf16_bits((float)bkk / dn);
             if (rnd & 1) {
                 fw[rnd >> 1] |= cb << 16;
@@ -822,7 +834,7 @@ template <int R, int CH, int NW>
 struct FeatOccupancy {
     static hipError_t run(int lds, bool co, int* blocks)
     {
-        if constexpr (CH != 1 || NW != 8) {
+        if constexpr (CH != 1 || NW == 4) {
             return hipErrorInvalidValue;
         } else {
             if (co)
@@ -834,7 +846,8 @@ struct FeatOccupancy {
     }
 };
 
-// FeatOccupancy through the (r, ch, nw) dispatcher: only (gray, 8 waves) exists
+// FeatOccupancy through the (r, ch, nw) dispatcher: only gray tiles of 8 or 12
+// waves exist
 template <int R, int CH, int NW>
 struct FeatOccupancyAny {
     static hipError_t run(int lds, bool co, int* blocks)
@@ -847,7 +860,7 @@ template <int R, int CH, int NW>
 struct FeatLauncher {
     static hipError_t run(const TileJob& job, const Tables& t, hipStream_t s)
     {
-        if constexpr (CH != 1 || NW != 8) {
+        if constexpr (CH != 1 || NW == 4) {
             return hipErrorInvalidValue;
         } else {
             const MfmaLayout lay = mfma_layout(R, 1, job.g.D, job.nb, NW);
