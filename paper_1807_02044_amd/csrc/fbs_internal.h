@@ -53,7 +53,7 @@ hipError_t launch_valu(const Geom& g, const Tables& t, CostSrc src, const uint8_
 
 // Fused TAD path on the matrix cores.
 struct MfmaCfg {
-    int nw;  // waves per workgroup: 4 (8x8 pixel tiles) or 8 (8x16)
+    int nw;  // waves per workgroup: 4, 8 or 12 (8x8, 8x16 or 8x24 pixel tiles)
     int nb;  // 16-disparity blocks per LDS slab
 };
 bool mfma_supported(const Geom& g);

@@ -655,12 +655,11 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     }
     if constexpr (FEAT) {
         // merge the four quarters' sorted lists: 8 rounds, each taking the
-        // smallest head (the lower quarter, hence the lower d, on a tie)
-        uint32_t fw[8];
-        const float dn = (float)(D - 1);
+        // smallest head key (keys are unique; on equal costs the lower
+        // quarter holds the lower disparity)
+        uint64_t sel[8];
 #pragma unroll
         for (int rnd = 0; rnd < 8; ++rnd) {
-            // the smallest head key of the four quarters (keys are unique)
             uint64_t best_key = 0;
             int bt = 0;
 #pragma unroll
@@ -678,24 +677,29 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
                 for (int i = 0; i < 7; ++i) tkey[i] = tkey[i + 1];
                 tkey[7] = ~0ull;
             }
-            const float bvv = __uint_as_float((uint32_t)(best_key >> 32));
-            const int bkk = (int)(uint32_t)best_key;
-            const uint32_t cb = bf16_bits(bvv / g.tau), ib = bf16_bits((float)bkk / dn);
-            if (rnd & 1) {
-                fw[rnd >> 1] |= cb << 16;
-                fw[4 + (rnd >> 1)] |= ib << 16;
-            } else {
-                fw[rnd >> 1] = cb;
-                fw[4 + (rnd >> 1)] = ib;
-            }
+            sel[rnd] = best_key;
         }
-        if (gq == 0 && pin) {
-            const uint32_t lb = bf16_bits((float)lp[0] / 255.0f);
-            uint4* dst = reinterpret_cast<uint4*>(job.feat + ((size_t)py * g.W + px) * 32);
-            dst[0] = make_uint4(fw[0], fw[1], fw[2], fw[3]);
-            dst[1] = make_uint4(fw[4], fw[5], fw[6], fw[7]);
-            dst[2] = make_uint4(lb, 0u, 0u, 0u);
-            dst[3] = make_uint4(0u, 0u, 0u, 0u);
+        // the pixel's four lanes share the conversions: quarter gq forms the
+        // features of ranks 2gq and 2gq + 1 and stores its quarter of the
+        // 64-byte record (dwords gq, 4 + gq, 8 + 2gq, 9 + 2gq)
+        uint64_t s0 = sel[0], s1 = sel[1];
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+            if (gq == q) {
+                s0 = sel[2 * q];
+                s1 = sel[2 * q + 1];
+            }
+        const float dn = (float)(D - 1);
+        const uint32_t cw = bf16_bits(__uint_as_float((uint32_t)(s0 >> 32)) / g.tau) |
+                            (bf16_bits(__uint_as_float((uint32_t)(s1 >> 32)) / g.tau) << 16);
+        const uint32_t iw = bf16_bits((float)(int)(uint32_t)s0 / dn) |
+                            (bf16_bits((float)(int)(uint32_t)s1 / dn) << 16);
+        if (pin) {
+            uint32_t* dst = reinterpret_cast<uint32_t*>(job.feat + ((size_t)py * g.W + px) * 32);
+            dst[gq] = cw;
+            dst[4 + gq] = iw;
+            const uint32_t lb = gq == 0 ? bf16_bits((float)lp[0] / 255.0f) : 0u;
+            *reinterpret_cast<uint2*>(dst + 8 + 2 * gq) = make_uint2(lb, 0u);
         }
     }
 }
