@@ -31,6 +31,8 @@
 // quarters are merged with lane shuffles at the end.
 #pragma once
 
+#include <type_traits>
+
 #include <algorithm>
 #include <atomic>
 
@@ -560,35 +562,57 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
         __syncthreads();
         build_slab(0, nblk);
         __syncthreads();
-        f4 ah[kCoMax], al[kCoMax];
+        // The chunk loop, with the block count and whether Sigma w is formed
+        // fixed at compile time for the common cases (NBK = 0 / DEN = 2: read
+        // at run time): then no branch separates the matrix instructions.
+        auto co_chunks = [&](auto nbk_c, auto den_c) {
+            constexpr int NBK = decltype(nbk_c)::value;
+            constexpr int DEN = decltype(den_c)::value;
+            const bool den_on = DEN == 2 ? want_den : DEN == 1;
+            f4 ah[kCoMax], al[kCoMax];
 #pragma unroll
-        for (int b = 0; b < kCoMax; ++b) {
-            ah[b] = f4{0.f, 0.f, 0.f, 0.f};
-            al[b] = ah[b];
-        }
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            h8 wh, wl;
-            chunk_weights(c, wh, wl);
-            if (want_den) {
-                dh = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, wh, dh, 0, 0, 0);
-                dl = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, wl, dl, 0, 0, 0);
+            for (int b = 0; b < kCoMax; ++b) {
+                ah[b] = f4{0.f, 0.f, 0.f, 0.f};
+                al[b] = ah[b];
             }
-            h8 a[kCoMax];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                h8 wh, wl;
+                chunk_weights(c, wh, wl);
+                if (den_on) {
+                    dh = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, wh, dh, 0, 0, 0);
+                    dl = __builtin_amdgcn_mfma_f32_16x16x32_f16(ones, wl, dl, 0, 0, 0);
+                }
+                h8 a[kCoMax];
+#pragma unroll
+                for (int b = 0; b < kCoMax; ++b)
+                    if (NBK ? b < NBK : b < nblk) a[b] = lds_h8<GW == 8>(plane0 + (size_t)(16 * b) * PS + a_off(c));
+#pragma unroll
+                for (int b = 0; b < kCoMax; ++b)
+                    if (NBK ? b < NBK : b < nblk)
+                        ah[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[b], wh, ah[b], 0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < kCoMax; ++b)
+                    if (NBK ? b < NBK : b < nblk)
+                        al[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[b], wl, al[b], 0, 0, 0);
+            }
+            if (den_on) rden = 1.0f / (dh[0] + dl[0]);
 #pragma unroll
             for (int b = 0; b < kCoMax; ++b)
-                if (b < nblk) a[b] = lds_h8<GW == 8>(plane0 + (size_t)(16 * b) * PS + a_off(c));
-#pragma unroll
-            for (int b = 0; b < kCoMax; ++b)
-                if (b < nblk) ah[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[b], wh, ah[b], 0, 0, 0);
-#pragma unroll
-            for (int b = 0; b < kCoMax; ++b)
-                if (b < nblk) al[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[b], wl, al[b], 0, 0, 0);
+                if (NBK ? b < NBK : b < nblk) wta_block(gq * Q + 4 * b, ah[b], al[b]);
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        if constexpr (FEAT) {
+            if (nblk == 6) co_chunks(std::integral_constant<int, 6>{}, I1{});
+            else co_chunks(I0{}, I1{});
+        } else {
+            if (!want_den && nblk == 4) co_chunks(std::integral_constant<int, 4>{}, I0{});
+            else if (!want_den && nblk == 6) co_chunks(std::integral_constant<int, 6>{}, I0{});
+            else if (!want_den && nblk == 2) co_chunks(I2{}, I0{});
+            else co_chunks(I0{}, I2{});
         }
-        if (want_den) rden = 1.0f / (dh[0] + dl[0]);
-#pragma unroll
-        for (int b = 0; b < kCoMax; ++b)
-            if (b < nblk) wta_block(gq * Q + 4 * b, ah[b], al[b]);
     } else {
         const int nslab = (nblk + nb - 1) / nb;
         for (int s = 0; s < nslab; ++s) {
@@ -723,7 +747,8 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma(TileJob job, Tables tb)
 
 // One workgroup per tile of one gray frame, with the surrogate's features.
 template <int R, int NW, bool CO>
-__global__ __launch_bounds__(64 * NW) void k_fbs_mfma_feat(TileJob job, Tables tb)
+// (8-wave tiles up to r = 4 are held to 128 registers: two workgroups per CU)
+__global__ __launch_bounds__(64 * NW, NW == 8 && R <= 4 ? 4 : 1) void k_fbs_mfma_feat(TileJob job, Tables tb)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     load_tables(tb, R, smem, 64 * NW);
@@ -838,7 +863,7 @@ template <int R, int CH, int NW>
 struct FeatOccupancy {
     static hipError_t run(int lds, bool co, int* blocks)
     {
-        if constexpr (CH != 1 || NW == 4) {
+        if constexpr (CH != 1 || NW == 4 || (NW == 12 && R > 6)) {
             return hipErrorInvalidValue;
         } else {
             if (co)
@@ -850,8 +875,8 @@ struct FeatOccupancy {
     }
 };
 
-// FeatOccupancy through the (r, ch, nw) dispatcher: only gray tiles of 8 or 12
-// waves exist
+// FeatOccupancy through the (r, ch, nw) dispatcher: only gray tiles of 8 waves,
+// or of 12 up to r = 6 (at r = 7 the 12-wave feature tile spills), exist
 template <int R, int CH, int NW>
 struct FeatOccupancyAny {
     static hipError_t run(int lds, bool co, int* blocks)
@@ -864,7 +889,7 @@ template <int R, int CH, int NW>
 struct FeatLauncher {
     static hipError_t run(const TileJob& job, const Tables& t, hipStream_t s)
     {
-        if constexpr (CH != 1 || NW == 4) {
+        if constexpr (CH != 1 || NW == 4 || (NW == 12 && R > 6)) {
             return hipErrorInvalidValue;
         } else {
             const MfmaLayout lay = mfma_layout(R, 1, job.g.D, job.nb, NW);
