@@ -49,14 +49,19 @@ def bf16(x) -> np.ndarray:
 def features(agg: np.ndarray, left: np.ndarray, d_min: int, tau: float) -> np.ndarray:
     """17-channel features [H][W][17] (float64, not rounded) from a [D][H][W] volume.
 
-    The cost channels are formed in float32 (cost / cap), as the kernel does,
-    before any BF16 rounding; selection ties go to the lower disparity.
+    Costs (>= 0) are taken in float32 with the low kbits of their bit pattern
+    cleared, kbits being the bit width of D - 1 (the room the kernels use for
+    the disparity index in a 32-bit sort key): the 8 lowest such costs,
+    ascending, ties to the lower disparity.  The cost channels are those
+    costs / cap in float32, before any BF16 rounding.
     """
     D, H, W = agg.shape
-    order = np.argsort(agg, axis=0, kind="stable")[:K_TOP]          # ascending, stable
-    top = np.take_along_axis(agg, order, axis=0)
+    kbits = max(D - 1, 1).bit_length()
+    bits = agg.astype(np.float32).view(np.uint32) & np.uint32(~((1 << kbits) - 1) & 0xFFFFFFFF)
+    order = np.argsort(bits, axis=0, kind="stable")[:K_TOP]         # ascending, stable
+    top = np.take_along_axis(bits, order, axis=0).view(np.float32)
     f = np.empty((H, W, 2 * K_TOP + 1))
-    f[..., :K_TOP] = np.moveaxis((top.astype(np.float32) / np.float32(tau)).astype(np.float64), 0, -1)
+    f[..., :K_TOP] = np.moveaxis((top / np.float32(tau)).astype(np.float64), 0, -1)
     denom = max(D - 1, 1)
     f[..., K_TOP:2 * K_TOP] = np.moveaxis(order.astype(np.float64) / denom, 0, -1)
     f[..., 2 * K_TOP] = left.astype(np.float64) / 255.0

@@ -69,27 +69,22 @@ __global__ __launch_bounds__(256) void k_sur_features(int W, int H, int D, float
     if (x >= W || y >= H) return;
     const size_t plane = (size_t)W * H;
     const float* a = agg + (size_t)y * W + x;
-    float bv[SUR_TOPK];
-    int bk[SUR_TOPK];
+    // keys: the cost's bits with the low kbits (the width of D - 1) replaced
+    // by the disparity index (costs are >= 0): ascending keys order by cost at
+    // that resolution, then by disparity
+    const int kbits = 32 - __builtin_clz((unsigned)max(D - 1, 1));
+    const uint32_t kmask = (1u << kbits) - 1u;
+    uint32_t key[SUR_TOPK];
 #pragma unroll
-    for (int i = 0; i < SUR_TOPK; ++i) {
-        bv[i] = __builtin_inff();
-        bk[i] = 0;
-    }
+    for (int i = 0; i < SUR_TOPK; ++i) key[i] = ~0u;
     for (int k = 0; k < D; ++k) {
-        const float v = a[(size_t)k * plane];
-        if (v < bv[SUR_TOPK - 1]) {
-            // insert after equal values: ties keep the lower disparity first
+        const uint32_t q = (__float_as_uint(a[(size_t)k * plane]) & ~kmask) | (uint32_t)k;
+        if (q < key[SUR_TOPK - 1]) {
 #pragma unroll
             for (int i = SUR_TOPK - 1; i >= 0; --i) {
-                const bool shift = i > 0 && v < bv[i > 0 ? i - 1 : 0];
-                if (shift) {
-                    bv[i] = bv[i - 1];
-                    bk[i] = bk[i - 1];
-                } else if (v < bv[i]) {
-                    bv[i] = v;
-                    bk[i] = k;
-                }
+                const bool shift = i > 0 && q < key[i > 0 ? i - 1 : 0];
+                if (shift) key[i] = key[i - 1];
+                else if (q < key[i]) key[i] = q;
             }
         }
     }
@@ -97,8 +92,10 @@ __global__ __launch_bounds__(256) void k_sur_features(int W, int H, int D, float
     const float dn = (float)(D - 1);
 #pragma unroll
     for (int i = 0; i < SUR_TOPK; i += 2) {
-        w[i / 2] = (uint32_t)to_bf16(bv[i] / tau) | ((uint32_t)to_bf16(bv[i + 1] / tau) << 16);
-        w[4 + i / 2] = (uint32_t)to_bf16((float)bk[i] / dn) | ((uint32_t)to_bf16((float)bk[i + 1] / dn) << 16);
+        w[i / 2] = (uint32_t)to_bf16(__uint_as_float(key[i] & ~kmask) / tau) |
+                   ((uint32_t)to_bf16(__uint_as_float(key[i + 1] & ~kmask) / tau) << 16);
+        w[4 + i / 2] = (uint32_t)to_bf16((float)(int)(key[i] & kmask) / dn) |
+                       ((uint32_t)to_bf16((float)(int)(key[i + 1] & kmask) / dn) << 16);
     }
     w[8] = to_bf16((float)L[(size_t)y * lstride + x] / 255.0f);
 #pragma unroll

@@ -396,15 +396,18 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     int bi = -1;
     bool need_cp = false;
     // FEAT: this lane's 8 lowest aggregated costs of its quarter, ascending,
-    // as keys (cost bits << 32 | k): costs are >= 0, so the keys order by
-    // cost and then by disparity
-    uint64_t tkey[FEAT ? 8 : 1];
+    // as 32-bit keys: the cost's bits with the low kbits (the width of D - 1)
+    // replaced by the disparity index k.  Costs are >= 0, so the keys order by
+    // cost at that resolution and then by disparity, and each key is unique.
+    const int kbits = 32 - __builtin_clz((unsigned)max(D - 1, 1));
+    const uint32_t kmask = (1u << kbits) - 1u;
+    uint32_t tkey[FEAT ? 8 : 1];
     if constexpr (FEAT) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) tkey[i] = ~0ull;
+        for (int i = 0; i < 8; ++i) tkey[i] = ~0u;
     }
-    auto ce = [](uint64_t& a, uint64_t& b) {  // compare-exchange: a <= b after
-        const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    auto ce = [](uint32_t& a, uint32_t& b) {  // compare-exchange: a <= b after
+        const uint32_t lo = min(a, b), hi = max(a, b);
         a = lo;
         b = hi;
     };
@@ -534,12 +537,12 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
             // list: the lowest 8 of list and block form a bitonic sequence
             // (list[0..3], min(list[4+i], blk[3-i])) that three
             // compare-exchange stages sort
-            uint64_t bk[4];
+            uint32_t bk[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = kb + j;
-                const float a = (k < D) ? ((acc_h[j] + acc_l[j]) * rden) * inv_scale : kInf;
-                bk[j] = k < D ? ((uint64_t)__float_as_uint(a) << 32) | (uint32_t)k : ~0ull;
+                const float a = ((acc_h[j] + acc_l[j]) * rden) * inv_scale;
+                bk[j] = k < D ? (__float_as_uint(a) & ~kmask) | (uint32_t)k : ~0u;
             }
             ce(bk[0], bk[1]);
             ce(bk[2], bk[3]);
@@ -547,7 +550,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
             ce(bk[1], bk[3]);
             ce(bk[1], bk[2]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) tkey[4 + i] = tkey[4 + i] < bk[3 - i] ? tkey[4 + i] : bk[3 - i];
+            for (int i = 0; i < 4; ++i) tkey[4 + i] = min(tkey[4 + i], bk[3 - i]);
 #pragma unroll
             for (int i = 0; i < 4; ++i) ce(tkey[i], tkey[i + 4]);
 #pragma unroll
@@ -679,34 +682,24 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     }
     if constexpr (FEAT) {
         // merge the four quarters' sorted lists: 8 rounds, each taking the
-        // smallest head key (keys are unique; on equal costs the lower
-        // quarter holds the lower disparity)
-        uint64_t sel[8];
+        // smallest head key; keys are unique, so the lane holding it pops it
+        uint32_t sel[8];
 #pragma unroll
         for (int rnd = 0; rnd < 8; ++rnd) {
-            uint64_t best_key = 0;
-            int bt = 0;
+            uint32_t best_key = __shfl(tkey[0], n);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const uint32_t hi = __shfl((uint32_t)(tkey[0] >> 32), n + 16 * t);
-                const uint32_t lo = __shfl((uint32_t)tkey[0], n + 16 * t);
-                const uint64_t key = ((uint64_t)hi << 32) | lo;
-                if (t == 0 || key < best_key) {
-                    best_key = key;
-                    bt = t;
-                }
-            }
-            if (gq == bt) {
+            for (int t = 1; t < 4; ++t) best_key = min(best_key, (uint32_t)__shfl(tkey[0], n + 16 * t));
+            if (tkey[0] == best_key) {
 #pragma unroll
                 for (int i = 0; i < 7; ++i) tkey[i] = tkey[i + 1];
-                tkey[7] = ~0ull;
+                tkey[7] = ~0u;
             }
             sel[rnd] = best_key;
         }
         // the pixel's four lanes share the conversions: quarter gq forms the
         // features of ranks 2gq and 2gq + 1 and stores its quarter of the
         // 64-byte record (dwords gq, 4 + gq, 8 + 2gq, 9 + 2gq)
-        uint64_t s0 = sel[0], s1 = sel[1];
+        uint32_t s0 = sel[0], s1 = sel[1];
 #pragma unroll
         for (int q = 1; q < 4; ++q)
             if (gq == q) {
@@ -714,10 +707,10 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
                 s1 = sel[2 * q + 1];
             }
         const float dn = (float)(D - 1);
-        const uint32_t cw = bf16_bits(__uint_as_float((uint32_t)(s0 >> 32)) / g.tau) |
-                            (bf16_bits(__uint_as_float((uint32_t)(s1 >> 32)) / g.tau) << 16);
-        const uint32_t iw = bf16_bits((float)(int)(uint32_t)s0 / dn) |
-                            (bf16_bits((float)(int)(uint32_t)s1 / dn) << 16);
+        const uint32_t cw = bf16_bits(__uint_as_float(s0 & ~kmask) / g.tau) |
+                            (bf16_bits(__uint_as_float(s1 & ~kmask) / g.tau) << 16);
+        const uint32_t iw = bf16_bits((float)(int)(s0 & kmask) / dn) |
+                            (bf16_bits((float)(int)(s1 & kmask) / dn) << 16);
         if (pin) {
             uint32_t* dst = reinterpret_cast<uint32_t*>(job.feat + ((size_t)py * g.W + px) * 32);
             dst[gq] = cw;

@@ -75,6 +75,23 @@ def test_features_sorted_with_ties_to_lower_d():
     assert f[0, 0, 16] == pytest.approx(51 / 255.0)
 
 
+def test_features_near_ties_at_key_resolution():
+    """Costs that differ only in the low kbits of their float32 pattern (kbits =
+    bit width of D - 1 = 4 here) are equal for the selection: the lower
+    disparity goes first and the truncated cost is reported."""
+    base = np.float32(3.0)
+    near = (base.view(np.uint32) + np.uint32(5)).view(np.float32)   # 3.0 plus 5 ulp
+    far = (base.view(np.uint32) + np.uint32(16)).view(np.float32)   # 3.0 plus 16 ulp
+    agg = np.full((10, 1, 1), 50.0)
+    agg[7, 0, 0] = base
+    agg[2, 0, 0] = near          # lower d than 7, slightly larger cost: a tie at key resolution
+    agg[0, 0, 0] = far           # a real difference: stays after both
+    f = S.features(agg, np.zeros((1, 1), dtype=np.uint8), d_min=0, tau=1.0)
+    np.testing.assert_array_equal(f[0, 0, 8:11], np.array([2, 7, 0]) / 9.0)
+    assert f[0, 0, 0] == f[0, 0, 1] == 3.0
+    assert f[0, 0, 2] == float(far)
+
+
 def test_l1_gradient_closed_form():
     pred = np.array([[1.0, 2.0], [3.0, 4.0]])
     label = np.array([[0.5, 2.0], [3.5, 1.0]])
