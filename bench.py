@@ -204,6 +204,19 @@ def surrogate(args, dev):
             stream.synchronize()
         return (time.perf_counter() - t0) / n
 
+    streams2 = [torch.cuda.Stream(device=dev) for _ in range(2)]
+
+    def timed2(fn):
+        """Frames alternate over two streams (two frames in flight); the first
+        pass warms up, the second is timed."""
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(n):
+                fn(i, streams2[i % 2])
+            torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
     def run_plain(i):
         L.fbs_run(pf, Ls[i], Rs[i], None, plain[i], None, None, stream)
 
@@ -255,11 +268,23 @@ def surrogate(args, dev):
                 sur.run_tiled(pc, pf, Ls[i], Rs[i], out, gpx, tfrac, stream)
                 tb.append(float(((out - plain[i]).abs() > 1.0).float().mean().item()))
                 teq.append(float((out == plain[i]).float().mean().item()))
+        # two frames in flight, for plain FBS and the tile-gated path alike
+        sur2 = L.FbsSurrogate(W, H, D)
+        sur2.set_params(np.load(SG.WEIGHTS))
+        outs = [out, torch.empty_like(out)]
+        surs = [sur, sur2]
+        t2_plain = timed2(lambda i, s: L.fbs_run(pf, Ls[i], Rs[i], None, plain[i], None, None, s))
+        t2 = timed2(lambda i, s: surs[i % 2].run_tiled(pc, pf, Ls[i], Rs[i], outs[i % 2], gpx,
+                                                       tfrac, s))
+        sur2.close()
         res["gate_tiles"] = {"gate_px": gpx, "tile_frac": tfrac, "frames_per_s": 1.0 / t,
                              "bad1_vs_plain": float(np.mean(tb)),
                              "bad1_vs_plain_max": float(np.max(tb)),
                              "pixels_equal_to_plain": float(np.mean(teq)),
                              "speedup_vs_plain": t_plain / t,
+                             "two_streams": {"plain_frames_per_s": 1.0 / t2_plain,
+                                             "frames_per_s": 1.0 / t2,
+                                             "speedup_vs_plain": t2_plain / t2},
                              "calibration": {k: tg[k] for k in ("train_frames", "target_bad1",
                                                                 "train_bad1_p90")}}
     sur.close()
