@@ -624,10 +624,11 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
             __syncthreads();  // every wave is done with the previous slab
             build_slab(b0, nbb);
             __syncthreads();
-            // blocks in pairs: two independent hi and two lo chains
-#pragma unroll 1
-            for (int bb = 0; bb < nbb; bb += 2) {
-                const bool two = bb + 1 < nbb;
+            // blocks in pairs: two independent hi and two lo chains, the
+            // pair count fixed per call so that no branch separates the
+            // matrix instructions; an odd last block runs alone
+            auto blocks = [&](int bb, auto two_c) {
+                constexpr bool TWO = decltype(two_c)::value;
                 f4 ah0 = {0.f, 0.f, 0.f, 0.f}, al0 = ah0, ah1 = ah0, al1 = ah0;
                 const _Float16* p0 = plane0 + (size_t)(16 * bb) * PS;
                 const _Float16* p1 = p0 + (size_t)16 * PS;
@@ -636,15 +637,19 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
                     const h8 a0 = lds_h8<GW == 8>(p0 + a_off(c));
                     ah0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, whi[c], ah0, 0, 0, 0);
                     al0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, wlo[c], al0, 0, 0, 0);
-                    if (two) {
+                    if constexpr (TWO) {
                         const h8 a1 = lds_h8<GW == 8>(p1 + a_off(c));
                         ah1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, whi[c], ah1, 0, 0, 0);
                         al1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, wlo[c], al1, 0, 0, 0);
                     }
                 }
                 wta_block(gq * Q + 4 * (b0 + bb), ah0, al0);
-                if (two) wta_block(gq * Q + 4 * (b0 + bb + 1), ah1, al1);
-            }
+                if constexpr (TWO) wta_block(gq * Q + 4 * (b0 + bb + 1), ah1, al1);
+            };
+            int bb = 0;
+#pragma unroll 1
+            for (; bb + 1 < nbb; bb += 2) blocks(bb, std::true_type{});
+            if (bb < nbb) blocks(bb, std::false_type{});
         }
     }
 
