@@ -95,6 +95,7 @@ struct BatchClass {
     const int2* items;
     int n_items;
     const int* n_dev;     // non-null: the queue length is read from here (persistent only)
+    int tiles_per_item;   // persistent: consecutive tiles of one pair per item (>= 1)
     int* counter;
     const uint8_t* const* L;
     const uint8_t* const* R;

@@ -52,6 +52,7 @@ struct fbs_plan {
 };
 
 namespace {
+constexpr int kTilesPerItem = 4;
 
 __global__ void k_zero(int* p, int n)
 {
@@ -261,6 +262,9 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
         }
     std::vector<BatchPair> pairs(n);
     std::vector<int2> items;
+    // persistent workgroups take kTilesPerItem consecutive tiles of a pair per
+    // queue item (one descriptor chain for them); per-tile mode one tile
+    const int per_item = (flags & FBS_PLAN_PER_TILE) ? 1 : kTilesPerItem;
     struct Span {
         int r, ch, nw, co, first, count, lds;
         Tables tb;
@@ -279,7 +283,7 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
             const Geom g = api_geom(&params[i]);
             const int tw = 2 * p->cfg[i].nw;
             const int tx = (g.W + tw - 1) / tw, ty = (g.H + 7) / 8;
-            for (int t = 0; t < tx * ty; ++t) items.push_back(make_int2(i, t));
+            for (int t = 0; t < tx * ty; t += per_item) items.push_back(make_int2(i, t));
             pairs[i].g = g;
             pairs[i].scap = mfma_scaled_cap(g);
             pairs[i].nb = p->cfg[i].nb;
@@ -326,6 +330,7 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
         const int per_cu = mfma_batch_blocks_per_cu(sp.r, sp.ch, sp.nw, sp.lds, sp.co != 0);
         bc.grid = std::max(1, std::min(sp.count, cus * per_cu));
         bc.one_wg_per_item = (flags & FBS_PLAN_PER_TILE) ? 1 : 0;
+        bc.tiles_per_item = per_item;
         bc.pairs = p->d_pairs;
         bc.items = p->d_items + sp.first;
         bc.n_items = sp.count;

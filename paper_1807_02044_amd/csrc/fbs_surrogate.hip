@@ -410,6 +410,7 @@ fbs_status fbs_surrogate_run_tiled(fbs_surrogate* s, const fbs_params* cheap,
     bc.tb = api_tables(full);
     bc.grid = s->cus * mfma_batch_blocks_per_cu(gf.r, gf.C, cfg.nw, bc.lds, bc.co != 0);
     bc.one_wg_per_item = 0;
+    bc.tiles_per_item = 1;
     bc.pairs = &s->job->pair;
     bc.items = s->items;
     bc.n_items = 0;

@@ -766,7 +766,8 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __r
                                                             int32_t* const* __restrict__ disps,
                                                             float* const* __restrict__ subs,
                                                             Tables tb,
-                                                            const int* __restrict__ n_dev)
+                                                            const int* __restrict__ n_dev,
+                                                            int tiles_per_item)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_next[2];
@@ -785,15 +786,22 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_batch(const BatchPair* __r
         // claim the next item now so the atomic's round trip overlaps this tile
         if (threadIdx.x == 0) s_next[buf ^ 1] = atomicAdd(counter, 1);
         buf ^= 1;
+        // an item is tiles_per_item consecutive tiles of one pair (fewer at
+        // the pair's end): the descriptor chain below is paid once for them
         const int2 w = items[it];
         const BatchPair& bp = pairs[w.x];
         TileJob job{bp.g, bp.scap, bp.nb, Ls[w.x], Rs[w.x], disps[w.x], subs[w.x], nullptr, nullptr};
-        // an opaque copy of the thread index per item keeps the compiler from
-        // hoisting the tile's index arithmetic out of the loop (it would stay
-        // live in registers across every item)
-        int tid;
-        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
-        mfma_tile<R, CH, NW, false, CO>(job, w.y % bp.tiles_x, w.y / bp.tiles_x, smem, tid);
+        const int tend = min(w.y + tiles_per_item, bp.tiles_x * ((bp.g.H + kTileH - 1) / kTileH));
+#pragma unroll 1
+        for (int t = w.y; t < tend; ++t) {
+            if (t > w.y) __syncthreads();  // every wave is done with the previous tile's LDS
+            // an opaque copy of the thread index per tile keeps the compiler from
+            // hoisting the tile's index arithmetic out of the loop (it would stay
+            // live in registers across every tile)
+            int tid;
+            asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+            mfma_tile<R, CH, NW, false, CO>(job, t % bp.tiles_x, t / bp.tiles_x, smem, tid);
+        }
     }
 }
 
@@ -915,7 +923,7 @@ hipError_t launch_batch_co(const BatchClass& bc, hipStream_t s)
     }
     hipLaunchKernelGGL((k_fbs_mfma_batch<R, CH, NW, CO>), dim3(bc.grid), dim3(64 * NW), bc.lds, s,
                        bc.pairs, bc.items, bc.n_items, bc.counter, bc.L, bc.R, bc.disp, bc.sub,
-                       bc.tb, bc.n_dev);
+                       bc.tb, bc.n_dev, std::max(1, bc.tiles_per_item));
     return hipGetLastError();
 }
 
