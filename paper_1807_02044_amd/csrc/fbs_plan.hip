@@ -342,21 +342,38 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
         p->classes.push_back(bc);
     }
 
-    // capture: reset the queue counters, then one persistent kernel per class
+    // capture: reset the queue counters, then one kernel per class; the class
+    // kernels are independent branches of the graph (fork after the reset,
+    // join at the end), so one class's last tiles overlap the next class
     if (!p->classes.empty()) {
+        const int nc = (int)p->classes.size();
         hipStream_t cs = nullptr;
-        bool cap = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
-                   hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
+        std::vector<hipStream_t> side(nc - 1, nullptr);
+        std::vector<hipEvent_t> ev(nc, nullptr);
+        bool cap = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+        for (int c = 0; c < nc && cap; ++c)
+            cap = hipEventCreateWithFlags(&ev[c], hipEventDisableTiming) == hipSuccess &&
+                  (c == 0 || hipStreamCreateWithFlags(&side[c - 1], hipStreamNonBlocking) == hipSuccess);
+        cap = cap && hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
         if (cap) {
-            const int nc = (int)p->classes.size();
             hipLaunchKernelGGL(k_zero, dim3((nc + 63) / 64), dim3(64), 0, cs, p->d_counters, nc);
-            for (const BatchClass& bc : p->classes) cap = cap && launch_mfma_batch(bc, cs) == hipSuccess;
+            cap = hipEventRecord(ev[0], cs) == hipSuccess;
+            for (int c = 1; c < nc && cap; ++c)
+                cap = hipStreamWaitEvent(side[c - 1], ev[0], 0) == hipSuccess &&
+                      launch_mfma_batch(p->classes[c], side[c - 1]) == hipSuccess &&
+                      hipEventRecord(ev[c], side[c - 1]) == hipSuccess;
+            cap = cap && launch_mfma_batch(p->classes[0], cs) == hipSuccess;
+            for (int c = 1; c < nc && cap; ++c) cap = hipStreamWaitEvent(cs, ev[c], 0) == hipSuccess;
             hipGraph_t gr = nullptr;
             const bool ended = hipStreamEndCapture(cs, &gr) == hipSuccess;
             cap = cap && ended && gr;
             if (gr) p->graph = gr;
             if (cap) cap = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
         }
+        for (hipStream_t q : side)
+            if (q) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
         if (cs) (void)hipStreamDestroy(cs);
         if (!cap) {
             release(p);
