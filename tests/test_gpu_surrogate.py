@@ -438,3 +438,32 @@ def test_run_tiled(W, H, D):
         v = fbs.params_for(wl.with_(radius=6, sigma_s=6.0), flags=L.FBS_F_FORCE_VALU)
         sur.run_tiled(cheap, v, Lt, Rt, out, 1.0, 0.1)
     sur.close()
+
+
+def test_run_tiled_two_objects_two_streams():
+    """Two surrogate objects on two streams, frames in flight together: each
+    result equals the same call made alone (no state shared between objects)."""
+    W, H, D = 96, 64, 24
+    frames = [_pair(W, H, D, seed=40 + i) for i in range(4)]
+    sur = [L.FbsSurrogate(W, H, D) for _ in range(2)]
+    for s_ in sur:
+        s_.set_params(pack(S.init_params(5)))
+    gate = 0.05
+    dev_pairs = [(torch.from_numpy(pr.left).to(DEV), torch.from_numpy(pr.right).to(DEV))
+                 for _, pr, _, _ in frames]
+    alone = []
+    for (wl, pr, cheap, full), (Lt, Rt) in zip(frames, dev_pairs):
+        o = torch.empty((H, W), dtype=torch.float32, device=DEV)
+        sur[0].run_tiled(cheap, full, Lt, Rt, o, gate, 0.3)
+        torch.cuda.synchronize()
+        alone.append(o.cpu().numpy())
+    streams = [torch.cuda.Stream(device=DEV) for _ in range(2)]
+    outs = [torch.full((H, W), -1.0, dtype=torch.float32, device=DEV) for _ in frames]
+    torch.cuda.synchronize()
+    for i, ((wl, pr, cheap, full), (Lt, Rt)) in enumerate(zip(frames, dev_pairs)):
+        sur[i % 2].run_tiled(cheap, full, Lt, Rt, outs[i], gate, 0.3, streams[i % 2])
+    torch.cuda.synchronize()
+    for i in range(len(frames)):
+        np.testing.assert_array_equal(outs[i].cpu().numpy(), alone[i], err_msg=f"frame {i}")
+    for s_ in sur:
+        s_.close()
