@@ -6,10 +6,12 @@
 // [H][W][32] (the 17 input channels padded with zeros to 32); sums are FP32.
 //
 //   k_sur_features     top-8 aggregated costs / disparities + intensity
+//   k_sur_net_fwd      inference: all four layers and the residual in one
+//                        launch, bit-identical to the per-layer kernels
 //   k_sur_conv<MODE>   32 -> 32 conv on the matrix cores (BF16 MFMA):
 //                        forward  out = relu(conv(in, W) + b)
 //                        backward out = conv(g, flip(W)^T) * [act > 0]
-//   k_sur_last_fwd     32 -> 1 conv, residual, L1 loss gradient (vector ALU)
+//   k_sur_last_fwd     32 -> 1 conv (matrix cores), residual, L1 loss gradient
 //   k_sur_last_bwd     gradient through the 32 -> 1 conv and the ReLU mask
 //   k_sur_wgrad        weight / bias gradients of a 32 -> 32 layer (vector ALU)
 //   k_sur_wgrad_last   weight / bias gradients of the 32 -> 1 layer
@@ -17,6 +19,7 @@
 //   k_sur_adam         Adam on the float32 master weights
 //   k_sur_pack         BF16 kernel copies of the master weights
 //   k_sur_gate         count of pixels where prediction and cheap differ
+//   k_sur_tile_gate    list of the full-radius tiles to rerun (tile-gated run)
 #include <algorithm>
 
 #include "fbs_internal.h"
