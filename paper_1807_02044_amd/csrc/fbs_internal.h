@@ -94,7 +94,7 @@ struct BatchClass {
     const BatchPair* pairs;
     const int2* items;
     int n_items;
-    const int* n_dev;     // non-null: the queue length is read from here (persistent only)
+    const int* n_dev;     // non-null: the list length is read from here (n_items: its bound)
     int tiles_per_item;   // persistent: consecutive tiles of one pair per item (>= 1)
     int* counter;
     const uint8_t* const* L;

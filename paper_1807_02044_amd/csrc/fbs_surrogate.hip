@@ -408,12 +408,14 @@ fbs_status fbs_surrogate_run_tiled(fbs_surrogate* s, const fbs_params* cheap,
     bc.co = mfma_use_co(gf.D, cfg.nb) ? 1 : 0;
     bc.lds = mfma_lds_bytes(gf, cfg.nb, cfg.nw);
     bc.tb = api_tables(full);
-    bc.grid = s->cus * mfma_batch_blocks_per_cu(gf.r, gf.C, cfg.nw, bc.lds, bc.co != 0);
-    bc.one_wg_per_item = 0;
+    // one workgroup per listed tile (the grid covers every tile; those past
+    // the list's end leave at once)
+    bc.grid = 0;
+    bc.one_wg_per_item = 1;
     bc.tiles_per_item = 1;
     bc.pairs = &s->job->pair;
     bc.items = s->items;
-    bc.n_items = 0;
+    bc.n_items = tiles_x * ((H + 7) / 8);
     bc.n_dev = s->qctr;
     bc.counter = s->qctr + 1;
     bc.L = &s->job->L;

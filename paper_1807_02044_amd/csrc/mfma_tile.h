@@ -814,9 +814,13 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma_items(const BatchPair* __r
                                                             const uint8_t* const* __restrict__ Rs,
                                                             int32_t* const* __restrict__ disps,
                                                             float* const* __restrict__ subs,
-                                                            Tables tb)
+                                                            Tables tb,
+                                                            const int* __restrict__ n_dev)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    // a list whose length a previous kernel wrote on the device: the grid
+    // covers its largest size and workgroups past the end leave at once
+    if (n_dev && (int)blockIdx.x >= __builtin_amdgcn_readfirstlane(*n_dev)) return;
     load_tables(tb, R, smem, 64 * NW);   // the class shares its weight tables
     const int2 w = items[blockIdx.x];
     const BatchPair& bp = pairs[w.x];
@@ -918,7 +922,7 @@ hipError_t launch_batch_co(const BatchClass& bc, hipStream_t s)
     if (bc.one_wg_per_item) {
         if (bc.n_items < 1) return hipSuccess;
         hipLaunchKernelGGL((k_fbs_mfma_items<R, CH, NW, CO>), dim3(bc.n_items), dim3(64 * NW),
-                           bc.lds, s, bc.pairs, bc.items, bc.L, bc.R, bc.disp, bc.sub, bc.tb);
+                           bc.lds, s, bc.pairs, bc.items, bc.L, bc.R, bc.disp, bc.sub, bc.tb, bc.n_dev);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_fbs_mfma_batch<R, CH, NW, CO>), dim3(bc.grid), dim3(64 * NW), bc.lds, s,
