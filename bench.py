@@ -34,7 +34,7 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0     # dense fp16 matrix peak
 MEASURED_TRAFFIC = {
     "slanted8_450x375_gray_d0-63_r7": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "f03041faba4dbe7cc28bb61d0097616ceafc3271f9d79d3088ecaaeeeafef2dc",
+        "sha256": "d6a5a65a1b05d2502c174ccbcd5795ac28c9c4e05fd69577eada823e4ffba9c1",
         "bytes_per_launch": 4.669e6,
     },
 }
