@@ -49,19 +49,18 @@ def bf16(x) -> np.ndarray:
 def features(agg: np.ndarray, left: np.ndarray, d_min: int, tau: float) -> np.ndarray:
     """17-channel features [H][W][17] (float64, not rounded) from a [D][H][W] volume.
 
-    Costs (>= 0) are taken in float32 with the low kbits of their bit pattern
-    cleared, kbits being the bit width of D - 1 (the room the kernels use for
-    the disparity index in a 32-bit sort key): the 8 lowest such costs,
-    ascending, ties to the lower disparity.  The cost channels are those
-    costs / cap in float32, before any BF16 rounding.
+    Per pixel, the 8 lowest aggregated costs in exact ascending order (equal
+    costs: the lower disparity first) divided by the cost cap, their
+    disparity indices (d - d_min) / (D - 1) in the same order, and the left
+    intensity / 255.  Costs are compared as given (float64 of the volume's
+    values); nothing is truncated or re-encoded.
     """
     D, H, W = agg.shape
-    kbits = max(D - 1, 1).bit_length()
-    bits = agg.astype(np.float32).view(np.uint32) & np.uint32(~((1 << kbits) - 1) & 0xFFFFFFFF)
-    order = np.argsort(bits, axis=0, kind="stable")[:K_TOP]         # ascending, stable
-    top = np.take_along_axis(bits, order, axis=0).view(np.float32)
+    a = np.asarray(agg, dtype=np.float64)
+    order = np.argsort(a, axis=0, kind="stable")[:K_TOP]            # ascending, ties to lower d
+    top = np.take_along_axis(a, order, axis=0)
     f = np.empty((H, W, 2 * K_TOP + 1))
-    f[..., :K_TOP] = np.moveaxis((top / np.float32(tau)).astype(np.float64), 0, -1)
+    f[..., :K_TOP] = np.moveaxis(top / float(tau), 0, -1)
     denom = max(D - 1, 1)
     f[..., K_TOP:2 * K_TOP] = np.moveaxis(order.astype(np.float64) / denom, 0, -1)
     f[..., 2 * K_TOP] = left.astype(np.float64) / 255.0
