@@ -15,6 +15,11 @@ Bilateral Stereo"):
 * :func:`wta_subpixel`  Section II-C (WTA) and Section II-D, Eq. (10)
 * :func:`fbs`           the four steps in order, left image as reference
 * :func:`fbs_pixels`    the same four steps at chosen pixels only
+* :func:`cost_right`    Section II-A: the right cost volume, C_R(u,v,d) = C_L(u+d,v,d)
+* :func:`fbs_right`     the four steps with the right image as reference
+* :func:`fbs_right_pixels`  the same at chosen right-image pixels
+* :func:`lrc`           Section II-D, Eq. (9): left-right consistency of two maps
+* :func:`fbs_lrc`       both maps, Eq. (9), and Eq. (10) on the surviving left pixels
 """
 from __future__ import annotations
 
@@ -99,8 +104,15 @@ def lib() -> ctypes.CDLL:
         h.orc_fbs.argtypes = [P, u8, u8, i32, f64, f64]
         h.orc_fbs_pixels.argtypes = [P, u8, u8, ctypes.c_int32, i32, i32, f64, i32, f64]
         h.orc_threads.argtypes = []
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        h.orc_cost_right.argtypes = [P, u8, u8, f64]
+        h.orc_fbs_right.argtypes = [P, u8, u8, i32, f64, f64]
+        h.orc_fbs_right_pixels.argtypes = [P, u8, u8, ctypes.c_int32, i32, i32, f64, i32, f64]
+        h.orc_lrc.argtypes = [P, i32, i32, ctypes.c_int32, u8p]
+        h.orc_fbs_lrc.argtypes = [P, u8, u8, ctypes.c_int32, i32, i32, u8p, f64]
         for f in (h.orc_cost, h.orc_weights, h.orc_aggregate, h.orc_wta_subpixel, h.orc_fbs,
-                  h.orc_fbs_pixels, h.orc_threads):
+                  h.orc_fbs_pixels, h.orc_threads, h.orc_cost_right, h.orc_fbs_right,
+                  h.orc_fbs_right_pixels, h.orc_lrc, h.orc_fbs_lrc):
             f.restype = ctypes.c_int
         _lib_handle = h
     return _lib_handle
@@ -230,3 +242,82 @@ def fbs_pixels(pb: Problem, left: np.ndarray, right: np.ndarray, xs, ys):
                               _i32(ys), _f64(agg), _i32(disp), _f64(sub))
     _check(rc, "fbs_pixels")
     return agg, disp, sub
+
+
+# ------------------------------------------------------------ right reference
+
+
+def cost_right(pb: Problem, left: np.ndarray, right: np.ndarray) -> np.ndarray:
+    """Right cost volume [D][H][W] (float64): C_R(u,v,d) = C_L(u+d,v,d)."""
+    H, W, _ = _shape(left)
+    if left.shape != right.shape:
+        raise ValueError("left/right shapes differ")
+    out = np.empty((pb.n_disp, H, W), dtype=np.float64)
+    L = np.ascontiguousarray(left)
+    R = np.ascontiguousarray(right)
+    _check(lib().orc_cost_right(ctypes.byref(_params(pb, L)), _u8(L), _u8(R), _f64(out)),
+           "cost_right")
+    return out
+
+
+def fbs_right(pb: Problem, left: np.ndarray, right: np.ndarray, want_agg: bool = False):
+    """Right-reference pipeline. Returns (disp, disp_sub[, agg]) of the right view."""
+    H, W, _ = _shape(left)
+    if left.shape != right.shape:
+        raise ValueError("left/right shapes differ")
+    L = np.ascontiguousarray(left)
+    R = np.ascontiguousarray(right)
+    disp = np.empty((H, W), dtype=np.int32)
+    sub = np.empty((H, W), dtype=np.float64)
+    agg = np.empty((pb.n_disp, H, W), dtype=np.float64) if want_agg else None
+    rc = lib().orc_fbs_right(ctypes.byref(_params(pb, L)), _u8(L), _u8(R), _i32(disp), _f64(sub),
+                             _f64(agg) if agg is not None else None)
+    _check(rc, "fbs_right")
+    return (disp, sub, agg) if want_agg else (disp, sub)
+
+
+def fbs_right_pixels(pb: Problem, left: np.ndarray, right: np.ndarray, xs, ys):
+    """Right-reference pipeline at chosen right-image pixels: (agg [n][D], disp, disp_sub)."""
+    L = np.ascontiguousarray(left)
+    R = np.ascontiguousarray(right)
+    xs = np.ascontiguousarray(xs, dtype=np.int32)
+    ys = np.ascontiguousarray(ys, dtype=np.int32)
+    n = int(xs.size)
+    agg = np.empty((n, pb.n_disp), dtype=np.float64)
+    disp = np.empty(n, dtype=np.int32)
+    sub = np.empty(n, dtype=np.float64)
+    rc = lib().orc_fbs_right_pixels(ctypes.byref(_params(pb, L)), _u8(L), _u8(R), n, _i32(xs),
+                                    _i32(ys), _f64(agg), _i32(disp), _f64(sub))
+    _check(rc, "fbs_right_pixels")
+    return agg, disp, sub
+
+
+def lrc(pb: Problem, disp_left: np.ndarray, disp_right: np.ndarray,
+        max_diff: int = 0) -> np.ndarray:
+    """Eq. (9) on two integer maps: uint8 [H][W], 1 where the left match survives."""
+    dl = np.ascontiguousarray(disp_left, dtype=np.int32)
+    dr = np.ascontiguousarray(disp_right, dtype=np.int32)
+    if dl.shape != dr.shape or dl.ndim != 2:
+        raise ValueError("maps must be [H][W] of one shape")
+    valid = np.empty(dl.shape, dtype=np.uint8)
+    fake = np.zeros(dl.shape, dtype=np.uint8)      # only the image shape is read
+    _check(lib().orc_lrc(ctypes.byref(_params(pb, fake)), _i32(dl), _i32(dr), int(max_diff),
+                         valid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))), "lrc")
+    return valid
+
+
+def fbs_lrc(pb: Problem, left: np.ndarray, right: np.ndarray, max_diff: int = 0):
+    """The paper's full path: (disp_left, disp_right, valid, disp_sub) with
+    disp_sub = Eq. (10) on the left map where Eq. (9) holds and -1 elsewhere."""
+    H, W, _ = _shape(left)
+    L = np.ascontiguousarray(left)
+    R = np.ascontiguousarray(right)
+    dl = np.empty((H, W), dtype=np.int32)
+    dr = np.empty((H, W), dtype=np.int32)
+    valid = np.empty((H, W), dtype=np.uint8)
+    sub = np.empty((H, W), dtype=np.float64)
+    rc = lib().orc_fbs_lrc(ctypes.byref(_params(pb, L)), _u8(L), _u8(R), int(max_diff), _i32(dl),
+                           _i32(dr), valid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                           _f64(sub))
+    _check(rc, "fbs_lrc")
+    return dl, dr, valid, sub

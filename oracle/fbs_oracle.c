@@ -30,6 +30,19 @@
  *   - WTA ties go to the lowest d; Eq. (10) is applied to the aggregated
  *     costs, and returns d* at d_min, d_max or when its denominator is <= 0.
  *
+ * Right reference (Section II-A, the right cost volume; Section II-C, WTA on
+ * both volumes; Section II-D, Eq. 9):
+ *   cost       the right volume holds, at (u,v,d), the cost of matching right
+ *              pixel (u,v) with left pixel (u+d,v), i.e. the left volume's
+ *              value at (u+d,v,d) - the two volumes store each cost once
+ *              each.  Where u+d is outside the image: TAD tau, NCC 2.
+ *   weights    Eqs. (7)-(8) with i(x,y) taken from the right image.
+ *   LRC        Eq. (9): a left pixel keeps its disparity d only if u-d is in
+ *              the image and the right map at (u-d,v) holds d (within an
+ *              optional tolerance, 0 = Eq. 9 as printed).
+ *   final map  Eq. (10) on the left aggregated costs where the check passes,
+ *              -1 where it fails (the match is removed).
+ *
  * Volumes are [D][H][W] with index d - d_min; weights are [H][W][(2r+1)^2]
  * in row-major tap order (dy outer, dx inner).  Images are HWC uint8 with a
  * row stride in bytes.
@@ -121,6 +134,16 @@ static double cost_at(const orc_params* p, const uint8_t* L, const uint8_t* R,
     return p->cost_type == ORC_NCC ? cost_ncc(p, L, R, x, y, d) : cost_tad(p, L, R, x, y, d);
 }
 
+/* Right-reference cost at right pixel (u,v) and disparity d: the match of
+ * right pixel u is left pixel u + d, so this is the left-reference cost at
+ * (u + d, v, d); where u + d leaves the image, the off-image value. */
+static double cost_right_at(const orc_params* p, const uint8_t* L, const uint8_t* R,
+                            int u, int v, int d)
+{
+    if (u + d >= p->width) return p->cost_type == ORC_NCC ? 2.0 : p->tau;
+    return cost_at(p, L, R, u + d, v, d);
+}
+
 /* Eqs. (7)-(8): weight of tap q = p + (dx,dy) for centre p; 0 off-image. */
 static double weight_at(const orc_params* p, const uint8_t* L, int u, int v, int dx, int dy)
 {
@@ -147,6 +170,19 @@ int orc_cost(const orc_params* p, const uint8_t* L, const uint8_t* R, double* co
         for (int k = 0; k < D; ++k)
             for (int x = 0; x < W; ++x)
                 cost[((size_t)k * H + y) * W + x] = cost_at(p, L, R, x, y, p->d_min + k);
+    return 0;
+}
+
+/* The right cost volume [D][H][W]: C_R(u,v,d) = C_L(u+d,v,d). */
+int orc_cost_right(const orc_params* p, const uint8_t* L, const uint8_t* R, double* cost)
+{
+    if (orc_check(p)) return -1;
+    const int W = p->width, H = p->height, D = p->d_max - p->d_min + 1;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y)
+        for (int k = 0; k < D; ++k)
+            for (int u = 0; u < W; ++u)
+                cost[((size_t)k * H + y) * W + u] = cost_right_at(p, L, R, u, y, p->d_min + k);
     return 0;
 }
 
@@ -255,6 +291,73 @@ int orc_fbs(const orc_params* p, const uint8_t* L, const uint8_t* R,
     return rc;
 }
 
+/* The right-reference pipeline: right cost volume, weights from the right
+ * image, Eq. (6), WTA and Eq. (10).  agg_out may be NULL. */
+int orc_fbs_right(const orc_params* p, const uint8_t* L, const uint8_t* R,
+                  int32_t* disp, double* disp_sub, double* agg_out)
+{
+    if (orc_check(p)) return -1;
+    const size_t N = (size_t)p->width * p->height;
+    const size_t D = (size_t)(p->d_max - p->d_min + 1);
+    const size_t T = (size_t)(2 * p->radius + 1) * (2 * p->radius + 1);
+    double* cost = (double*)malloc(N * D * sizeof(double));
+    double* w = (double*)malloc(N * T * sizeof(double));
+    double* agg = agg_out ? agg_out : (double*)malloc(N * D * sizeof(double));
+    int rc = 0;
+    if (!cost || !w || !agg) {
+        rc = -2;
+    } else {
+        orc_cost_right(p, L, R, cost);
+        orc_weights(p, R, w);
+        orc_aggregate(p, cost, w, agg);
+        orc_wta_subpixel(p, agg, disp, disp_sub);
+    }
+    free(cost);
+    free(w);
+    if (!agg_out) free(agg);
+    return rc;
+}
+
+/* Eq. (9): valid[v][u] = 1 when u - dl(u,v) >= 0 and
+ * |dr(u - dl(u,v), v) - dl(u,v)| <= max_diff, else 0. */
+int orc_lrc(const orc_params* p, const int32_t* dl, const int32_t* dr, int32_t max_diff,
+            uint8_t* valid)
+{
+    if (orc_check(p) || max_diff < 0) return -1;
+    const int W = p->width, H = p->height;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const int d = dl[(size_t)y * W + x];
+            const int u = x - d;
+            int ok = 0;
+            if (u >= 0 && u < W) {
+                const int diff = dr[(size_t)y * W + u] - d;
+                ok = (diff <= max_diff && -diff <= max_diff);
+            }
+            valid[(size_t)y * W + x] = (uint8_t)ok;
+        }
+    return 0;
+}
+
+/* The paper's full path: both disparity maps, the LRC check of Eq. (9) and
+ * Eq. (10) on the left map; disp_sub is -1 where the check removes the match. */
+int orc_fbs_lrc(const orc_params* p, const uint8_t* L, const uint8_t* R, int32_t max_diff,
+                int32_t* disp_l, int32_t* disp_r, uint8_t* valid, double* disp_sub)
+{
+    if (orc_check(p) || max_diff < 0) return -1;
+    const size_t N = (size_t)p->width * p->height;
+    double* sub_r = (double*)malloc(N * sizeof(double));
+    int rc = sub_r ? 0 : -2;
+    if (!rc) rc = orc_fbs(p, L, R, disp_l, disp_sub, NULL);
+    if (!rc) rc = orc_fbs_right(p, L, R, disp_r, sub_r, NULL);
+    if (!rc) rc = orc_lrc(p, disp_l, disp_r, max_diff, valid);
+    if (!rc)
+        for (size_t i = 0; i < N; ++i)
+            if (!valid[i]) disp_sub[i] = -1.0;
+    free(sub_r);
+    return rc;
+}
+
 /* The same pipeline evaluated at n chosen pixels only (xs[i], ys[i]), for
  * images too large for full volumes.  agg is [n][D]. */
 int orc_fbs_pixels(const orc_params* p, const uint8_t* L, const uint8_t* R, int32_t n,
@@ -279,6 +382,39 @@ int orc_fbs_pixels(const orc_params* p, const uint8_t* L, const uint8_t* R, int3
                     int qx = x + dx, qy = y + dy;
                     if (qx < 0 || qx >= p->width || qy < 0 || qy >= p->height) continue;
                     num += weight_at(p, L, x, y, dx, dy) * cost_at(p, L, R, qx, qy, p->d_min + k);
+                }
+            a[k] = num / den;
+        }
+        wta_subpixel_one(p, a, 1, disp + i, disp_sub + i);
+    }
+    return 0;
+}
+
+/* The right-reference pipeline at n chosen right-image pixels (weights from
+ * the right image, costs of the right volume).  agg is [n][D]. */
+int orc_fbs_right_pixels(const orc_params* p, const uint8_t* L, const uint8_t* R, int32_t n,
+                         const int32_t* xs, const int32_t* ys, double* agg, int32_t* disp,
+                         double* disp_sub)
+{
+    if (orc_check(p)) return -1;
+    const int r = p->radius, D = p->d_max - p->d_min + 1;
+    for (int i = 0; i < n; ++i)
+        if (xs[i] < 0 || xs[i] >= p->width || ys[i] < 0 || ys[i] >= p->height) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < n; ++i) {
+        const int x = xs[i], y = ys[i];
+        double* a = agg + (size_t)i * D;
+        double den = 0.0;
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) den += weight_at(p, R, x, y, dx, dy);
+        for (int k = 0; k < D; ++k) {
+            double num = 0.0;
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx) {
+                    int qx = x + dx, qy = y + dy;
+                    if (qx < 0 || qx >= p->width || qy < 0 || qy >= p->height) continue;
+                    num += weight_at(p, R, x, y, dx, dy) *
+                           cost_right_at(p, L, R, qx, qy, p->d_min + k);
                 }
             a[k] = num / den;
         }

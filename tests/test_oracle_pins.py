@@ -454,3 +454,132 @@ def test_invalid_parameters_raise():
     with pytest.raises(ValueError):
         oracle.fbs(Problem(0, 3, 1, 1.0, 1.0, cost_type=NCC),
                    np.zeros((4, 8, 3), np.uint8), np.zeros((4, 8, 3), np.uint8))
+
+
+# ------------------------------------ f1: right volume (dual storage) and LRC
+
+
+@pytest.mark.parametrize("channels,cost_type", [(1, TAD), (3, TAD), (1, NCC)])
+def test_right_volume_is_the_left_volume_stored_again(channels, cost_type):
+    """Section II-A: the left volume's value at (u, v, d) is the right
+    volume's at (u - d, v, d); right positions whose match u + d leaves the
+    image hold the off-image cost."""
+    rng = _rng(21 + channels + 5 * cost_type)
+    shape = (7, 19) if channels == 1 else (7, 19, 3)
+    L = rng.integers(0, 256, shape, dtype=np.uint8)
+    R = rng.integers(0, 256, shape, dtype=np.uint8)
+    pb = Problem(2, 8, 1, 2.0, 9.0, tau=37.0, cost_type=cost_type)
+    cl = oracle.cost(pb, L, R)
+    cr = oracle.cost_right(pb, L, R)
+    W = L.shape[1]
+    off = 2.0 if cost_type == NCC else 37.0
+    for k, d in enumerate(range(pb.d_min, pb.d_max + 1)):
+        np.testing.assert_array_equal(cr[k][:, :W - d], cl[k][:, d:])
+        np.testing.assert_array_equal(cr[k][:, W - d:], off)
+
+
+def test_right_tad_hand_worked():
+    """C_R(u, d) = min(|R(u) - L(u + d)|, tau), tau where u + d >= W."""
+    L = np.array([[10, 50, 200, 0]], dtype=np.uint8)
+    R = np.array([[12, 90, 30, 255]], dtype=np.uint8)
+    pb = Problem(0, 2, 0, 1.0, 1.0, tau=40.0)
+    c = oracle.cost_right(pb, L, R)
+    want = np.array([
+        [2, 40, 40, 40],        # d=0: |12-10|, |90-50|, |30-200|, |255-0|
+        [38, 40, 30, 40],       # d=1: |12-50|, |90-200|, |30-0|, off
+        [40, 40, 40, 40],       # d=2: |12-200|, |90-0|, off, off
+    ], dtype=np.float64)
+    np.testing.assert_array_equal(c[:, 0, :], want)
+
+
+@pytest.mark.parametrize("channels,cost_type", [(1, TAD), (3, TAD), (1, NCC)])
+def test_right_reference_is_the_mirrored_left_reference(channels, cost_type):
+    """Mirroring both views left-right and swapping them turns the right
+    reference into the (independently pinned) left reference: right pixel u
+    matching left pixel u + d becomes left pixel W-1-u matching right pixel
+    W-1-u-d.  Maps agree exactly (up to exact ties), volumes to rounding."""
+    rng = _rng(31 + channels + 7 * cost_type)
+    shape = (11, 27) if channels == 1 else (11, 27, 3)
+    L = rng.integers(0, 256, shape, dtype=np.uint8)
+    R = np.clip(np.roll(L, -3, axis=1).astype(int) + rng.integers(-9, 10, shape), 0, 255
+                ).astype(np.uint8)
+    pb = Problem(0, 7, 2, 2.5, 11.0, tau=30.0, cost_type=cost_type)
+    dr, sr, ar = oracle.fbs_right(pb, L, R, want_agg=True)
+    Lm = np.ascontiguousarray(R[:, ::-1])
+    Rm = np.ascontiguousarray(L[:, ::-1])
+    dm, sm, am = oracle.fbs(pb, Lm, Rm, want_agg=True)
+    np.testing.assert_allclose(ar, am[:, :, ::-1], rtol=1e-12, atol=1e-12)
+    dm, sm = dm[:, ::-1], sm[:, ::-1]
+    diff = dr != dm
+    if diff.any():   # only exact ties may pick differently
+        ys, xs = np.nonzero(diff)
+        a1 = ar[dr[ys, xs] - pb.d_min, ys, xs]
+        a2 = ar[dm[ys, xs] - pb.d_min, ys, xs]
+        np.testing.assert_allclose(a1, a2, rtol=1e-12)
+    np.testing.assert_allclose(sr[~diff], sm[~diff], atol=1e-9)
+
+
+def test_lrc_hand_worked():
+    """Eq. (9) on a 1x6 pair of maps, worked by hand."""
+    dl = np.array([[0, 1, 1, 3, 2, 2]], dtype=np.int32)
+    dr = np.array([[0, 1, 2, 0, 2, 1]], dtype=np.int32)
+    pb = Problem(0, 3, 0, 1.0, 1.0)
+    # x=0: u=0, dr=0 == 0 ok; x=1: u=0, dr=0 != 1; x=2: u=1, dr=1 == 1 ok;
+    # x=3: u=0, dr=0 != 3; x=4: u=2, dr=2 == 2 ok; x=5: u=3, dr=0 != 2
+    np.testing.assert_array_equal(oracle.lrc(pb, dl, dr)[0], [1, 0, 1, 0, 1, 0])
+    # with tolerance 1: x=1 (|0-1| = 1) also passes; x=5 (|0-2| = 2) still fails
+    np.testing.assert_array_equal(oracle.lrc(pb, dl, dr, max_diff=1)[0], [1, 1, 1, 0, 1, 0])
+    # a disparity pointing left of the image never passes
+    np.testing.assert_array_equal(oracle.lrc(pb, np.array([[1, 3, 0, 0, 0, 0]], np.int32),
+                                             np.zeros((1, 6), np.int32))[0], [0, 0, 1, 1, 1, 1])
+
+
+@pytest.mark.parametrize("channels", [1, 3])
+def test_fronto_plane_both_maps_and_lrc(channels):
+    """Noise-free plane at d0: the left map is d0 where x - r >= d0, the right
+    map is d0 where u + r + d0 <= W - 1, and the LRC keeps every left pixel
+    with d0 + r <= x <= W - 1 - r."""
+    d0, r = 5, 2
+    L, R = scenes.textured_fronto_pair(40, 14, d0, seed=3, channels=channels)
+    pb = Problem(0, 9, r, 3.0, 12.0, tau=60.0)
+    dl, dr, valid, sub = oracle.fbs_lrc(pb, L, R)
+    W = L.shape[1]
+    assert np.all(dl[:, d0 + r:] == d0)
+    assert np.all(dr[:, :W - r - d0] == d0)
+    assert np.all(valid[:, d0 + r:W - r] == 1)
+    # Eq. 10 stays within half a pixel of d*; removed matches read -1
+    assert np.all(np.abs(sub[:, d0 + r:W - r] - d0) <= 0.5)
+    assert np.all(sub[valid == 0] == -1.0)
+
+
+@pytest.mark.parametrize("cost_type", [TAD, NCC])
+def test_fbs_lrc_is_composition(cost_type):
+    rng = _rng(41 + cost_type)
+    L = rng.integers(0, 256, (9, 22), dtype=np.uint8)
+    R = np.clip(np.roll(L, -2, axis=1).astype(int) + rng.integers(-20, 21, L.shape), 0, 255
+                ).astype(np.uint8)
+    pb = Problem(0, 6, 1, 2.0, 10.0, cost_type=cost_type)
+    dl, dr, valid, sub = oracle.fbs_lrc(pb, L, R, max_diff=0)
+    d1, s1 = oracle.fbs(pb, L, R)
+    d2, _ = oracle.fbs_right(pb, L, R)
+    v = oracle.lrc(pb, d1, d2)
+    np.testing.assert_array_equal(dl, d1)
+    np.testing.assert_array_equal(dr, d2)
+    np.testing.assert_array_equal(valid, v)
+    np.testing.assert_array_equal(sub, np.where(v == 1, s1, -1.0))
+    assert 0 < valid.sum() < valid.size
+
+
+@pytest.mark.parametrize("cost_type", [TAD, NCC])
+def test_right_per_pixel_entry_matches_volumes(cost_type):
+    rng = _rng(51 + cost_type)
+    L = rng.integers(0, 256, (10, 17), dtype=np.uint8)
+    R = rng.integers(0, 256, (10, 17), dtype=np.uint8)
+    pb = Problem(1, 6, 2, 2.0, 8.0, cost_type=cost_type)
+    d, s, a = oracle.fbs_right(pb, L, R, want_agg=True)
+    xs = np.array([0, 3, 16, 8, 12], dtype=np.int32)
+    ys = np.array([0, 9, 5, 2, 7], dtype=np.int32)
+    ap, dp, sp = oracle.fbs_right_pixels(pb, L, R, xs, ys)
+    np.testing.assert_allclose(ap, a[:, ys, xs].T, rtol=1e-13)
+    np.testing.assert_array_equal(dp, d[ys, xs])
+    np.testing.assert_allclose(sp, s[ys, xs], atol=1e-12)
