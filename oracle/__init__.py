@@ -20,6 +20,8 @@ Bilateral Stereo"):
 * :func:`fbs_right_pixels`  the same at chosen right-image pixels
 * :func:`lrc`           Section II-D, Eq. (9): left-right consistency of two maps
 * :func:`fbs_lrc`       both maps, Eq. (9), and Eq. (10) on the surviving left pixels
+* :func:`wmf`           weighted median filter of a disparity map (Section II-D)
+* :func:`wmf_cumulative`  window weights below / up to a candidate median
 """
 from __future__ import annotations
 
@@ -110,9 +112,12 @@ def lib() -> ctypes.CDLL:
         h.orc_fbs_right_pixels.argtypes = [P, u8, u8, ctypes.c_int32, i32, i32, f64, i32, f64]
         h.orc_lrc.argtypes = [P, i32, i32, ctypes.c_int32, u8p]
         h.orc_fbs_lrc.argtypes = [P, u8, u8, ctypes.c_int32, i32, i32, u8p, f64]
+        h.orc_wmf.argtypes = [P, u8, i32, i32]
+        h.orc_wmf_cumulative.argtypes = [P, u8, i32, i32, f64, f64, f64]
         for f in (h.orc_cost, h.orc_weights, h.orc_aggregate, h.orc_wta_subpixel, h.orc_fbs,
                   h.orc_fbs_pixels, h.orc_threads, h.orc_cost_right, h.orc_fbs_right,
-                  h.orc_fbs_right_pixels, h.orc_lrc, h.orc_fbs_lrc):
+                  h.orc_fbs_right_pixels, h.orc_lrc, h.orc_fbs_lrc, h.orc_wmf,
+                  h.orc_wmf_cumulative):
             f.restype = ctypes.c_int
         _lib_handle = h
     return _lib_handle
@@ -321,3 +326,34 @@ def fbs_lrc(pb: Problem, left: np.ndarray, right: np.ndarray, max_diff: int = 0)
                            _f64(sub))
     _check(rc, "fbs_lrc")
     return dl, dr, valid, sub
+
+
+# ------------------------------------------------------ weighted median filter
+
+
+def wmf(pb: Problem, image: np.ndarray, disp_in: np.ndarray) -> np.ndarray:
+    """Weighted median of int disparities over each (2 radius + 1)^2 window,
+    weights of Eqs. (7)-(8) from `image`; values outside [d_min, d_max] are
+    holes; -1 where a window holds no valid value."""
+    img = np.ascontiguousarray(image)
+    H, W, _ = _shape(img)
+    din = np.ascontiguousarray(disp_in, dtype=np.int32)
+    if din.shape != (H, W):
+        raise ValueError("map and image shapes differ")
+    out = np.empty((H, W), dtype=np.int32)
+    _check(lib().orc_wmf(ctypes.byref(_params(pb, img)), _u8(img), _i32(din), _i32(out)), "wmf")
+    return out
+
+
+def wmf_cumulative(pb: Problem, image: np.ndarray, disp_in: np.ndarray, m: np.ndarray):
+    """(below, upto, total) window weights for candidate medians m [H][W]."""
+    img = np.ascontiguousarray(image)
+    H, W, _ = _shape(img)
+    din = np.ascontiguousarray(disp_in, dtype=np.int32)
+    mm = np.ascontiguousarray(m, dtype=np.int32)
+    below = np.empty((H, W), dtype=np.float64)
+    upto = np.empty((H, W), dtype=np.float64)
+    total = np.empty((H, W), dtype=np.float64)
+    _check(lib().orc_wmf_cumulative(ctypes.byref(_params(pb, img)), _u8(img), _i32(din), _i32(mm),
+                                    _f64(below), _f64(upto), _f64(total)), "wmf_cumulative")
+    return below, upto, total

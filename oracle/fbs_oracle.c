@@ -43,6 +43,15 @@
  *   final map  Eq. (10) on the left aggregated costs where the check passes,
  *              -1 where it fails (the match is removed).
  *
+ * Weighted median filter (Section II-D names weighted median filtering among
+ * the refinement steps, without using it): each pixel's output is the
+ * weighted median of the disparities in its (2r+1)^2 window, with the
+ * weights of Eqs. (7)-(8) from the reference image; values outside
+ * [d_min, d_max] are holes that take no part; a window without any valid
+ * value gives -1.  The weighted median is the smallest window value m whose
+ * cumulative weight (the weights of values <= m) reaches half of the
+ * window's total weight.
+ *
  * Volumes are [D][H][W] with index d - d_min; weights are [H][W][(2r+1)^2]
  * in row-major tap order (dy outer, dx inner).  Images are HWC uint8 with a
  * row stride in bytes.
@@ -78,6 +87,18 @@ static int orc_check(const orc_params* p)
     } else {
         return -1;
     }
+    return 0;
+}
+
+/* Checks for the map filters, where the disparity range only labels holes. */
+static int orc_check_filter(const orc_params* p)
+{
+    if (!p) return -1;
+    if (p->width <= 0 || p->height <= 0) return -1;
+    if (p->channels != 1 && p->channels != 3) return -1;
+    if (p->row_stride < p->width * p->channels) return -1;
+    if (p->d_min < 0 || p->d_max < p->d_min || p->radius < 0) return -1;
+    if (!(p->gamma_d > 0.0) || !(p->gamma_r > 0.0)) return -1;
     return 0;
 }
 
@@ -424,6 +445,101 @@ int orc_fbs_right_pixels(const orc_params* p, const uint8_t* L, const uint8_t* R
 }
 
 /* Number of OpenMP threads the oracle runs on. */
+typedef struct {
+    int32_t value;
+    double weight;
+} wmf_item;
+
+static int wmf_cmp(const void* a, const void* b)
+{
+    const int32_t va = ((const wmf_item*)a)->value, vb = ((const wmf_item*)b)->value;
+    return (va > vb) - (va < vb);
+}
+
+/* Weighted median filter of an integer disparity map (see the header). */
+int orc_wmf(const orc_params* p, const uint8_t* img, const int32_t* din, int32_t* dout)
+{
+    if (orc_check_filter(p)) return -1;
+    const int W = p->width, H = p->height, r = p->radius;
+    const size_t T = (size_t)(2 * r + 1) * (2 * r + 1);
+    int rc = 0;
+#pragma omp parallel
+    {
+        wmf_item* it = (wmf_item*)malloc(T * sizeof(wmf_item));
+        if (!it) {
+#pragma omp atomic write
+            rc = -2;
+        }
+#pragma omp for schedule(static)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                if (!it) continue;
+                size_t n = 0;
+                double total = 0.0;
+                for (int dy = -r; dy <= r; ++dy)
+                    for (int dx = -r; dx <= r; ++dx) {
+                        const int qx = x + dx, qy = y + dy;
+                        if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                        const int32_t v = din[(size_t)qy * W + qx];
+                        if (v < p->d_min || v > p->d_max) continue;
+                        it[n].value = v;
+                        it[n].weight = weight_at(p, img, x, y, dx, dy);
+                        total += it[n].weight;
+                        ++n;
+                    }
+                int32_t out = -1;
+                if (n > 0) {
+                    qsort(it, n, sizeof(wmf_item), wmf_cmp);
+                    double cum = 0.0;
+                    for (size_t i = 0; i < n; ++i) {
+                        cum += it[i].weight;
+                        /* the last item of a run of equal values decides */
+                        if (i + 1 < n && it[i + 1].value == it[i].value) continue;
+                        if (cum >= 0.5 * total) {
+                            out = it[i].value;
+                            break;
+                        }
+                    }
+                }
+                dout[(size_t)y * W + x] = out;
+            }
+        free(it);
+    }
+    return rc;
+}
+
+/* For a candidate map m (one value per pixel): the window weights of valid
+ * values below m, of valid values up to m, and the total (Eqs. 7-8 weights
+ * from the reference image, as for orc_wmf).  m is a weighted median of the
+ * pixel's window exactly when below < total / 2 <= upto. */
+int orc_wmf_cumulative(const orc_params* p, const uint8_t* img, const int32_t* din,
+                       const int32_t* m, double* below, double* upto, double* total)
+{
+    if (orc_check_filter(p)) return -1;
+    const int W = p->width, H = p->height, r = p->radius;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const size_t o = (size_t)y * W + x;
+            double b = 0.0, u = 0.0, t = 0.0;
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx) {
+                    const int qx = x + dx, qy = y + dy;
+                    if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                    const int32_t v = din[(size_t)qy * W + qx];
+                    if (v < p->d_min || v > p->d_max) continue;
+                    const double w = weight_at(p, img, x, y, dx, dy);
+                    t += w;
+                    if (v < m[o]) b += w;
+                    if (v <= m[o]) u += w;
+                }
+            below[o] = b;
+            upto[o] = u;
+            total[o] = t;
+        }
+    return 0;
+}
+
 int orc_threads(void)
 {
 #ifdef _OPENMP

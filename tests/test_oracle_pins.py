@@ -583,3 +583,90 @@ def test_right_per_pixel_entry_matches_volumes(cost_type):
     np.testing.assert_allclose(ap, a[:, ys, xs].T, rtol=1e-13)
     np.testing.assert_array_equal(dp, d[ys, xs])
     np.testing.assert_allclose(sp, s[ys, xs], atol=1e-12)
+
+
+# ------------------------------------------ f4: weighted median filter (II-D)
+
+
+def test_wmf_uniform_weights_is_the_lower_median():
+    """With uniform weights (gamma = inf) the weighted median is the lower
+    median of the window's valid values: numpy's sort of each window."""
+    rng = _rng(41)
+    H, W, r = 11, 13, 2
+    img = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    d = rng.integers(0, 9, (H, W)).astype(np.int32)
+    d[rng.random((H, W)) < 0.2] = -1                      # holes
+    pb = Problem(0, 8, r, math.inf, math.inf)
+    got = oracle.wmf(pb, img, d)
+    for y in range(H):
+        for x in range(W):
+            win = d[max(0, y - r):y + r + 1, max(0, x - r):x + r + 1].ravel()
+            v = np.sort(win[win >= 0])
+            want = -1 if v.size == 0 else int(v[(v.size + 1) // 2 - 1])
+            assert got[y, x] == want, (y, x, v)
+
+
+def test_wmf_hand_worked_weights():
+    """3x1 window, gray, hand-computed weights: w = exp(-dx^2/gd^2) exp(-dI^2/gr^2)."""
+    img = np.array([[100, 100, 110]], dtype=np.uint8)
+    d = np.array([[5, 2, 9]], dtype=np.int32)
+    pb = Problem(0, 9, 1, 1.0, 10.0)
+    got = oracle.wmf(pb, img, d)
+    # centre pixel 1: weights 1 (itself, d=2), exp(-1) (left, d=5),
+    # exp(-1) * exp(-1) (right, d=9, dI = 10); half = (1 + e^-1 + e^-2) / 2 = 0.751
+    # sorted values 2 (w 1) -> cum 1 >= 0.751: median 2
+    assert got[0, 1] == 2
+    # pixel 0: itself (d=5, w 1), right (d=2, w e^-1); total 1.368, half 0.684;
+    # sorted 2 (cum 0.368), 5 (cum 1.368): median 5
+    assert got[0, 0] == 5
+    # pixel 2: itself (d=9, w 1), left (d=2, w e^-1 * e^-1 = 0.135): median 9
+    assert got[0, 2] == 9
+    # a heavier neighbour pulls the median: gamma_d large, equal intensities
+    img2 = np.full((1, 3), 50, dtype=np.uint8)
+    pb2 = Problem(0, 9, 1, 1e6, 10.0)
+    d2 = np.array([[7, 1, 7]], dtype=np.int32)
+    assert oracle.wmf(pb2, img2, d2)[0, 1] == 7           # two votes for 7, one for 1
+
+
+def test_wmf_constant_map_holes_and_all_holes():
+    rng = _rng(43)
+    img = rng.integers(0, 256, (9, 10), dtype=np.uint8)
+    pb = Problem(0, 15, 2, 3.0, 10.0)
+    d = np.full((9, 10), 6, dtype=np.int32)
+    d[3:5, 4:6] = -1                                        # small hole
+    got = oracle.wmf(pb, img, d)
+    assert (got == 6).all()                                 # filled from its neighbours
+    assert (oracle.wmf(pb, img, np.full((9, 10), -1, np.int32)) == -1).all()
+    # values above d_max are holes too
+    assert (oracle.wmf(pb, img, np.full((9, 10), 16, np.int32)) == -1).all()
+
+
+def test_wmf_range_weight_zero_keeps_equal_intensities():
+    """gamma_r -> 0: only neighbours of the centre's intensity carry weight,
+    so the output is the lower median of those neighbours' values."""
+    img = np.array([[10, 10, 200, 10, 200],
+                    [200, 10, 200, 200, 10]], dtype=np.uint8)
+    d = np.array([[1, 2, 9, 3, 9],
+                  [9, 4, 9, 9, 5]], dtype=np.int32)
+    pb = Problem(0, 9, 2, 1e9, 1e-3)
+    got = oracle.wmf(pb, img, d)
+    for y in range(2):
+        for x in range(5):
+            ys, xs = np.mgrid[max(0, y - 2):min(2, y + 3), max(0, x - 2):min(5, x + 3)]
+            same = img[ys, xs] == img[y, x]
+            v = np.sort(d[ys, xs][same])
+            assert got[y, x] == v[(v.size + 1) // 2 - 1], (y, x)
+
+
+def test_wmf_cumulative_brackets_the_median():
+    """The oracle's median sits where the cumulative weight crosses half:
+    below < total/2 <= upto, and one value lower would not reach half."""
+    rng = _rng(47)
+    img = rng.integers(0, 256, (14, 17, 3), dtype=np.uint8)
+    d = rng.integers(2, 12, (14, 17)).astype(np.int32)
+    pb = Problem(2, 11, 3, 2.5, 12.0)
+    m = oracle.wmf(pb, img, d)
+    below, upto, total = oracle.wmf_cumulative(pb, img, d, m)
+    assert np.all(below < 0.5 * total) and np.all(upto >= 0.5 * total)
+    b2, u2, _ = oracle.wmf_cumulative(pb, img, d, m - 1)
+    assert np.all(u2 < 0.5 * total)
