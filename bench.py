@@ -2,11 +2,14 @@
 """Benchmark of the fused fast-bilateral-stereo path on one MI355X.
 
 One step = one ``fbs_run`` (cost, weights, Eq. 6 aggregation, WTA, Eq. 10)
-over the 450x375 gray, 64-disparity, 15x15-window slanted-plane pair, with
-both images already resident in HBM.  Prints ONE JSON line with frames/s,
-pixel*disparity*tap rate, the roofline of the fused kernel measured live with
-HIP events on the stream it runs on, and the FP64 CPU oracle timed on the
-host's cores as a reported baseline.
+over the 1400x1000 RGB, 160-disparity, 21x21-window scene of 20 slanted
+planes and 5 blobs (the largest single-GPU workload), with both images already
+resident in HBM.  Prints ONE JSON line with frames/s, pixel*disparity*tap
+rate, the roofline of the fused kernel measured live with HIP events on the
+stream it runs on, and the FP64 CPU oracle timed on the host's cores as a
+reported baseline.  Extra keys: the two smaller single-pair workloads, the
+end-to-end rate with the host transfers, the left-right path (Eq. 9), the
+64-pair batched plan and the learned surrogate.
 """
 from __future__ import annotations
 
@@ -40,6 +43,31 @@ MEASURED_TRAFFIC = {
 }
 
 
+# Counter-derived utilisation of the fused kernel (rocprofv3 PMC runs of the
+# profiled command): VALU issue and matrix-pipe busy shares of the SIMD time
+# of one launch.  Valid only for the kernel source they were taken on.
+MEASURED_UTIL = {}
+
+
+def _sources_sha(sources):
+    import hashlib
+    h = hashlib.sha256()
+    try:
+        for src in sources:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+    except OSError:
+        return None
+    return h.hexdigest()
+
+
+def measured_utilisation(workload: str):
+    m = MEASURED_UTIL.get(workload)
+    if not m or _sources_sha(m["sources"]) != m["sha256"]:
+        return None
+    return {k: v for k, v in m.items() if k not in ("sources", "sha256")}
+
+
 def measured_traffic(workload: str):
     import hashlib
     m = MEASURED_TRAFFIC.get(workload)
@@ -60,7 +88,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
+    ap.add_argument("--workload", default="large", choices=["tiny", "mid", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--force-valu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -70,7 +98,17 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate comparison")
-    ap.add_argument("--surrogate-frames", type=int, default=16)
+    ap.add_argument("--surrogate-frames", type=int, default=200,
+                    help="held-out pairs of the surrogate evaluation")
+    ap.add_argument("--no-two-streams", action="store_true",
+                    help="skip the two-frames-in-flight leg (profiles of single-stream launches)")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="skip the smaller single-pair workloads")
+    ap.add_argument("--no-e2e", action="store_true",
+                    help="skip the end-to-end leg with host transfers")
+    ap.add_argument("--no-lr", action="store_true",
+                    help="skip the left-right path (both views and Eq. 9)")
+    ap.add_argument("--lr-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed loop, copy this many MiB device to device once "
                          "(a kernel of known traffic that calibrates rocprofv3 byte counters)")
@@ -105,6 +143,8 @@ def batched(args, dev):
     Rs = [torch.from_numpy(b).to(dev) for _, b in imgs]
     Ds = [torch.empty((w.height, w.width), dtype=torch.int32, device=dev) for w in wls]
     Ss = [torch.empty((w.height, w.width), dtype=torch.float32, device=dev) for w in wls]
+    Ds_seq = [torch.empty_like(t) for t in Ds]
+    Ss_seq = [torch.empty_like(t) for t in Ss]
     # persistent plan: fbs_run's heuristic configurations (most resident waves);
     # per-tile plan: tuned ones.  The tuner times each shape alone, and its
     # per-shape optimum helps the per-tile launch but not the persistent one,
@@ -133,10 +173,18 @@ def batched(args, dev):
 
     def sequential():
         for i in range(len(wls)):
-            L.fbs_run(params[i], Ls[i], Rs[i], Ds[i], Ss[i], None, None, stream)
+            L.fbs_run(params[i], Ls[i], Rs[i], Ds_seq[i], Ss_seq[i], None, None, stream)
+
+    def equal_pairs():
+        """Pairs whose graph outputs equal the sequential ones bit for bit."""
+        torch.cuda.synchronize()
+        return sum(int(torch.equal(Ds[i], Ds_seq[i]) and
+                       torch.equal(Ss[i].view(torch.int32), Ss_seq[i].view(torch.int32)))
+                   for i in range(len(wls)))
 
     ms_graph = timed(graph)
     ms_seq = timed(sequential)
+    eq_persistent = equal_pairs()
     t0 = time.perf_counter()
     plan_pt = L.FbsPlan(params, tune_cache=args.tune_cache, tune=True, per_tile=True)
     plan_pt_s = time.perf_counter() - t0
@@ -144,8 +192,14 @@ def batched(args, dev):
     def graph_per_tile():
         plan_pt.launch(Ls, Rs, Ds, Ss, stream)
 
+    for t in Ds + Ss:
+        t.fill_(-1)
     ms_graph_pt = timed(graph_per_tile)
+    eq_per_tile = equal_pairs()
     plan_pt.close()
+    if eq_persistent != len(wls) or eq_per_tile != len(wls):
+        raise RuntimeError(f"batched outputs differ from fbs_run: persistent {eq_persistent}, "
+                           f"per-tile {eq_per_tile} of {len(wls)} pairs bit-identical")
     cfgs = [plan.pair_config(i) for i in range(len(wls))]
     launches = plan.num_launches()
     plan.close()
@@ -160,6 +214,7 @@ def batched(args, dev):
         "speedup": ms_seq / ms_graph, "host_launches_graph": launches,
         "per_tile_graph_ms": ms_graph_pt, "per_tile_speedup": ms_seq / ms_graph_pt,
         "host_launches_sequential": n,
+        "bitwise_equal_pairs": {"persistent": eq_persistent, "per_tile": eq_per_tile},
         "waves_per_wg": sorted({c[1] for c in cfgs}), "slab_blocks": sorted({c[2] for c in cfgs}),
         "scene_gen_s": gen_s, "plan_create_s": plan_s, "per_tile_plan_create_s": plan_pt_s,
         "configs": "persistent: fbs_run heuristic; per-tile: tuned (FBS_PLAN_TUNE)",
@@ -324,6 +379,128 @@ def cpu_baseline(wl, pair, target_s: float):
     }
 
 
+def time_fused(L, p, Ld, Rd, disp, sub, ws, stream, steps, warmup):
+    """Wall time of `steps` fbs_run calls bracketed by synchronisations, then
+    per-launch kernel times from HIP events on the kernel's stream over a
+    second pass of the same launches."""
+    import torch
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            L.fbs_run(p, Ld, Rd, disp, sub, None, ws, stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            L.fbs_run(p, Ld, Rd, disp, sub, None, ws, stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for i in range(steps):
+            ev[i][0].record(stream)
+            L.fbs_run(p, Ld, Rd, disp, sub, None, ws, stream)
+            ev[i][1].record(stream)
+        stream.synchronize()
+    kern_ms = sorted(a.elapsed_time(b) for a, b in ev)
+    return wall, kern_ms
+
+
+def extra_config(name, args, dev, force_valu):
+    """One smaller single-pair workload: frames/s and the kernel time."""
+    import torch
+    from paper_1807_02044_amd import _lib as L
+    from paper_1807_02044_amd import scenes
+    import paper_1807_02044_amd as fbs
+    wl = scenes.workload(name)
+    pair = scenes.make_pair(wl)
+    p = fbs.params_for(wl, flags=L.FBS_F_FORCE_VALU if force_valu else 0)
+    Ld = torch.from_numpy(pair.left).to(dev)
+    Rd = torch.from_numpy(pair.right).to(dev)
+    disp = torch.empty((wl.height, wl.width), dtype=torch.int32, device=dev)
+    sub = torch.empty((wl.height, wl.width), dtype=torch.float32, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    steps = max(20, min(200, args.steps * 10))
+    wall, kern_ms = time_fused(L, p, Ld, Rd, disp, sub, fbs.workspace(p, dev), stream, steps, 10)
+    avg = sum(kern_ms) / len(kern_ms)
+    return {"workload": wl.name, "frames_per_s": steps / wall,
+            "gpix_disp_tap_per_s": wl.work_taps * steps / wall / 1e9,
+            "kernel_avg_ms": avg, "kernel": "k_fbs_mfma" if L.fbs_run_variant(p) else "k_valu",
+            "achieved_tflops": 2.0 * wl.work_taps / (avg * 1e-3) / 1e12, "steps": steps}
+
+
+def end_to_end(args, dev, wl, pair, p, stream):
+    """Images from pinned host memory to HBM, the fused run, both maps back."""
+    import torch
+    from paper_1807_02044_amd import _lib as L
+    import paper_1807_02044_amd as fbs
+    Lh = torch.from_numpy(pair.left).pin_memory()
+    Rh = torch.from_numpy(pair.right).pin_memory()
+    Ld, Rd = torch.empty_like(Lh, device=dev), torch.empty_like(Rh, device=dev)
+    disp = torch.empty((wl.height, wl.width), dtype=torch.int32, device=dev)
+    sub = torch.empty((wl.height, wl.width), dtype=torch.float32, device=dev)
+    disp_h = torch.empty(disp.shape, dtype=torch.int32).pin_memory()
+    sub_h = torch.empty(sub.shape, dtype=torch.float32).pin_memory()
+    ws = fbs.workspace(p, dev)
+    steps = max(5, args.steps)
+
+    def step():
+        Ld.copy_(Lh, non_blocking=True)
+        Rd.copy_(Rh, non_blocking=True)
+        L.fbs_run(p, Ld, Rd, disp, sub, None, ws, stream)
+        disp_h.copy_(disp, non_blocking=True)
+        sub_h.copy_(sub, non_blocking=True)
+
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            step()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+    nbytes = 2 * Lh.numel() + 8 * wl.width * wl.height
+    return {"frames_per_s": steps / wall, "ms_per_frame": wall * 1e3 / steps,
+            "host_bytes_per_frame": nbytes, "steps": steps,
+            "includes": "H2D of both images (pinned), fbs_run, D2H of disp and disp_sub, "
+                        "one stream, frames back to back"}
+
+
+def left_right(args, dev, wl, pair):
+    """The paper's path for both views: right run, left run, Eq. 9, Eq. 10."""
+    import torch
+    from paper_1807_02044_amd import _lib as L
+    import paper_1807_02044_amd as fbs
+    p = fbs.params_for(wl)
+    Ld = torch.from_numpy(pair.left).to(dev)
+    Rd = torch.from_numpy(pair.right).to(dev)
+    H, W = wl.height, wl.width
+    dl = torch.empty((H, W), dtype=torch.int32, device=dev)
+    dr = torch.empty_like(dl)
+    valid = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    sub = torch.empty((H, W), dtype=torch.float32, device=dev)
+    ws = torch.empty(L.fbs_lr_workspace_bytes(p), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    steps = max(3, args.lr_steps)
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            L.fbs_run_lr(p, Ld, Rd, 0, dl, dr, valid, sub, ws, stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            L.fbs_run_lr(p, Ld, Rd, 0, dl, dr, valid, sub, ws, stream)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+    kept = float(valid.float().mean().item())
+    return {"workload": wl.name, "frames_per_s": steps / wall,
+            "gpix_disp_tap_per_s": 2 * wl.work_taps * steps / wall / 1e9,
+            "mde_per_s": W * H * wl.n_disp * steps / wall / 1e6,
+            "lrc_kept_fraction": kept, "max_diff": 0, "steps": steps,
+            "includes": "fbs_run_lr: image mirror, right-reference run, left-reference run, "
+                        "Eq. 9 and Eq. 10 (two volumes' work)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -353,35 +530,25 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
 
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            L.fbs_run(p, Ld, Rd, disp, sub, None, ws, stream)
-        stream.synchronize()
-        # per-launch events on the kernel's own stream
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            ev[i][0].record(stream)
-            L.fbs_run(p, Ld, Rd, disp, sub, None, ws, stream)
-            ev[i][1].record(stream)
-        stream.synchronize()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-    # the same steps with two frames in flight (alternating streams, own
-    # outputs): what a serving loop sees once one frame's last tiles overlap
-    # the next frame's first
-    st2 = [torch.cuda.Stream(device=dev) for _ in range(2)]
-    outs2 = [(torch.empty_like(disp), torch.empty_like(sub), fbs.workspace(p, dev)) for _ in range(2)]
-    for rep in range(2):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            d2, s2, w2 = outs2[i % 2]
-            L.fbs_run(p, Ld, Rd, d2, s2, None, w2, st2[i % 2])
-        torch.cuda.synchronize()
-        wall2 = time.perf_counter() - t0
+    wall, kern_ms = time_fused(L, p, Ld, Rd, disp, sub, ws, stream, args.steps, args.warmup)
+    two_streams = None
+    if not args.no_two_streams:
+        # the same steps with two frames in flight (alternating streams, own
+        # outputs): what a serving loop sees once one frame's last tiles
+        # overlap the next frame's first
+        st2 = [torch.cuda.Stream(device=dev) for _ in range(2)]
+        outs2 = [(torch.empty_like(disp), torch.empty_like(sub), fbs.workspace(p, dev))
+                 for _ in range(2)]
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                d2, s2, w2 = outs2[i % 2]
+                L.fbs_run(p, Ld, Rd, d2, s2, None, w2, st2[i % 2])
+            torch.cuda.synchronize()
+            wall2 = time.perf_counter() - t0
+        two_streams = {"frames_per_s": args.steps / wall2,
+                       "gpix_disp_tap_per_s": wl.work_taps * args.steps / wall2 / 1e9}
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 20
         src = torch.ones(n, dtype=torch.uint8, device=dev)
@@ -390,7 +557,6 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    kern_ms = sorted(a.elapsed_time(b) for a, b in ev)
     avg_ms = sum(kern_ms) / len(kern_ms)
     ms_per_step = wall * 1e3 / args.steps
     fps = args.steps / wall
@@ -407,15 +573,21 @@ def main():
         roof = {"bound": "alu", "peak": PEAK_FP32_VALU_TFLOPS}
         dtype = "f32"
         kname = "k_valu"
+    traffic = measured_traffic(wl.name) if variant == 1 else None
     roof.update({"achieved": achieved_tflops, "unit": "TFLOP/s",
                  "frac": achieved_tflops / roof["peak"],
-                 "traffic": measured_traffic(wl.name) if variant == 1 else None,
+                 "traffic": traffic,
                  "kernel": kname, "kernel_avg_ms": avg_ms,
                  "kernel_p10_ms": kern_ms[len(kern_ms) // 10],
                  "kernel_p90_ms": kern_ms[(9 * len(kern_ms)) // 10],
-                 "flops_per_launch": flops})
-    two_streams = {"frames_per_s": args.steps / wall2,
-                   "gpix_disp_tap_per_s": taps * args.steps / wall2 / 1e9}
+                 "flops_per_launch": flops,
+                 "algorithmic_bytes_per_launch": (2 * wl.channels + 8) * wl.width * wl.height})
+    if traffic:
+        roof["hbm_gbs"] = traffic / (avg_ms * 1e-3) / 1e9
+        roof["hbm_frac"] = roof["hbm_gbs"] / PEAK_HBM_GBS
+    util = measured_utilisation(wl.name) if variant == 1 else None
+    if util:
+        roof.update(util)
     out = {
         "metric": METRIC,
         "value": fps,
@@ -437,9 +609,18 @@ def main():
         },
         "gpix_disp_tap_per_s": taps * fps / 1e9,
         "mde_per_s": wl.width * wl.height * wl.n_disp * fps / 1e6,
-        "two_streams": two_streams,
         "roofline": roof,
     }
+    if two_streams:
+        out["two_streams"] = two_streams
+    if not args.no_extra_configs:
+        out["other_configs"] = [extra_config(n, args, dev, args.force_valu)
+                                for n in ("tiny", "mid") if n != wl.name.split("_")[0]
+                                and n != args.workload]
+    if not args.no_e2e:
+        out["end_to_end"] = end_to_end(args, dev, wl, pair, p, stream)
+    if not args.no_lr:
+        out["left_right"] = left_right(args, dev, wl, pair)
     if not args.no_batched:
         out["batched"] = batched(args, dev)
     if not args.no_surrogate:

@@ -107,9 +107,11 @@ fbs_status fbs_cost(const fbs_params* p, const uint8_t* left, const uint8_t* rig
                     float* cost, void* workspace, void* stream);
 
 /* Aggregation step, Section II-B, Eq. 6 with the weights of Eqs. 7-8 taken
- * from the left image.  cost: volume [D][H][W] (any float values);
- * agg: volume [D][H][W] written in full; cost and agg must not overlap. */
-fbs_status fbs_aggregate(const fbs_params* p, const uint8_t* left, const float* cost,
+ * from the reference image: the left image for the left volume, the right
+ * image for the right volume of fbs_cost_lr.  cost: volume [D][H][W] (any
+ * float values); agg: volume [D][H][W] written in full; cost and agg must not
+ * overlap. */
+fbs_status fbs_aggregate(const fbs_params* p, const uint8_t* reference, const float* cost,
                          float* agg, void* stream);
 
 /* Optimisation and refinement, Sections II-C and II-D (Eq. 10).
@@ -130,6 +132,63 @@ fbs_status fbs_run(const fbs_params* p, const uint8_t* left, const uint8_t* righ
 /* Which fused kernel fbs_run picks for `p`: 1 = matrix-core (MFMA) kernel,
  * 0 = vector-ALU kernel.  Host only; FBS_E_* on invalid `p`. */
 int fbs_run_variant(const fbs_params* p);
+
+/* ---- Both views: right volume, right map, left-right check ----
+ *
+ * Right reference (Section II-A, II-C): the right volume holds at (u, v, d)
+ * the cost of right pixel (u, v) against left pixel (u + d, v), i.e. the left
+ * volume's value at (u + d, v, d) (TAD cap / NCC 2 where u + d >= W); it is
+ * aggregated with the weights of Eqs. 7-8 from the right image, and its WTA
+ * gives the right map (ties to the lowest d).  Eq. 9 (Section II-D): a left
+ * pixel (x, y) keeps its disparity d when x - d is in the image and
+ * |right(x - d, y) - d| <= max_diff (0 = the equality printed in Eq. 9); where
+ * it fails the match is removed.  */
+
+/* Cost step with dual storage (Section II-A): each cost is computed once and
+ * written to both volumes, cost_left[d][y][x] and cost_right[d][y][x - d];
+ * right entries with x = u + d >= W get the off-image value.  Both volumes
+ * [D][H][W], written in full, must not overlap; workspace as for fbs_cost. */
+fbs_status fbs_cost_lr(const fbs_params* p, const uint8_t* left, const uint8_t* right,
+                       float* cost_left, float* cost_right, void* workspace, void* stream);
+
+/* Eq. 9 on two integer maps (any source, e.g. fbs_wta_subpixel of the left
+ * and the right aggregated volumes).  valid[H][W] (uint8, may be NULL)
+ * receives 1 where the left match survives, else 0; disp_sub (float32, may be
+ * NULL) is overwritten with -1 where the check fails and left unchanged where
+ * it holds.  Only width, height, d_min, d_max of `p` are read. */
+fbs_status fbs_lrc(const fbs_params* p, const int32_t* disp_left, const int32_t* disp_right,
+                   int32_t max_diff, uint8_t* valid, float* disp_sub, void* stream);
+
+/* Weighted median filter, the refinement step Section II-D names beside the
+ * left-right check: disp_out[y][x] is the weighted median of the values of
+ * disp_in in the (2 radius + 1)^2 window around (x, y), each weighted by
+ * Eqs. 7-8 (sigma_s, sigma_r) from the reference image - the smallest
+ * window value whose cumulative weight (weights of values <= it) reaches half
+ * the window's total.  Values outside [d_min, d_max] are holes (e.g. the -1
+ * left by a failed check, or a map masked with fbs_lrc's valid): they take no
+ * part, and a window without any valid value gives -1.  From `p` only the
+ * image geometry, d_min, d_max (d_max may exceed width here), radius and
+ * sigma_s, sigma_r are read.  disp_in, disp_out: int32 [H][W], not
+ * overlapping.  Weights and sums in float32. */
+fbs_status fbs_wmf(const fbs_params* p, const uint8_t* reference, const int32_t* disp_in,
+                   int32_t* disp_out, void* stream);
+
+/* Bytes of device workspace fbs_run_lr needs for `p` (mirrored image copies,
+ * the right map, the left map, and NCC's block sums).  Host only. */
+fbs_status fbs_lr_workspace_bytes(const fbs_params* p, size_t* bytes);
+
+/* The paper's whole path for both views, fused (Sections II-A to II-D):
+ * the right-reference run, the left-reference run, Eq. 9 and Eq. 10.
+ * disp_left, disp_right: int32 [H][W] integer maps; valid: uint8 [H][W]
+ * (Eq. 9); disp_sub: float32 [H][W], Eq. 10 on the left aggregated costs where
+ * Eq. 9 holds and -1 where it fails.  Any output may be NULL.  workspace:
+ * fbs_lr_workspace_bytes(p) bytes, 256-byte aligned, required.  The right run
+ * is the left-reference kernel applied to the left-right mirrored pair
+ * (mirrored right image as reference), so both views use the same kernels
+ * and arithmetic as fbs_run.  Calls sharing one workspace must not overlap. */
+fbs_status fbs_run_lr(const fbs_params* p, const uint8_t* left, const uint8_t* right,
+                      int32_t max_diff, int32_t* disp_left, int32_t* disp_right, uint8_t* valid,
+                      float* disp_sub, void* workspace, void* stream);
 
 /* ---- Batched plans: many pairs of uneven sizes in one graph launch ---- */
 
@@ -161,7 +220,12 @@ fbs_status fbs_plan_create(fbs_plan** out, int32_t n, const fbs_params* params,
  * pointers (images as described by the pair's params; dense int32 / float32
  * [H][W] maps).  Enqueues a pointer upload, one graph launch and, for pairs
  * the matrix cores cannot take, one vector-ALU launch each, on `stream`.
- * Waits (on the host) only for the previous launch's pointer upload. */
+ * A plan holds one device pointer table and one set of work-queue counters,
+ * so launches of one plan are ordered: each launch waits on the device for
+ * the previous one to finish, whatever stream either was given (launches on
+ * two streams therefore do not overlap; use one plan per stream for that).
+ * Waits (on the host) only for the previous launch's pointer upload.  Calls
+ * on one plan from several host threads must be serialised by the caller. */
 fbs_status fbs_plan_launch(fbs_plan* plan, const uint8_t* const* left,
                            const uint8_t* const* right, int32_t* const* disp,
                            float* const* disp_sub, void* stream);

@@ -10,7 +10,8 @@ from __future__ import annotations
 
 from typing import Optional, Tuple
 
-__all__ = ["params_for", "run", "cost", "aggregate", "wta_subpixel", "workspace"]
+__all__ = ["params_for", "run", "cost", "aggregate", "wta_subpixel", "workspace", "run_lr",
+           "cost_lr", "lrc", "wmf"]
 
 
 def params_for(wl, cost_type: int = 0, ncc_radius: int = 1, flags: int = 0):
@@ -72,3 +73,47 @@ def wta_subpixel(p, agg, stream=None):
     sub = torch.empty((H, W), dtype=torch.float32, device=agg.device)
     _lib.fbs_wta_subpixel(p, agg, disp, sub, stream)
     return disp, sub
+
+
+def run_lr(p, left, right, max_diff: int = 0, stream=None):
+    """fbs_run_lr -> (disp_left, disp_right int32, valid uint8, disp_sub float32)."""
+    import torch
+    from . import _lib
+    H, W = p.height, p.width
+    dev = _dev(left)
+    dl = torch.empty((H, W), dtype=torch.int32, device=dev)
+    dr = torch.empty((H, W), dtype=torch.int32, device=dev)
+    valid = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    sub = torch.empty((H, W), dtype=torch.float32, device=dev)
+    ws = torch.empty(_lib.fbs_lr_workspace_bytes(p), dtype=torch.uint8, device=dev)
+    _lib.fbs_run_lr(p, left, right, max_diff, dl, dr, valid, sub, ws, stream)
+    return dl, dr, valid, sub
+
+
+def cost_lr(p, left, right, stream=None):
+    """fbs_cost_lr -> (cost_left, cost_right) float32 [D][H][W]."""
+    import torch
+    from . import _lib
+    D = p.d_max - p.d_min + 1
+    cl = torch.empty((D, p.height, p.width), dtype=torch.float32, device=_dev(left))
+    cr = torch.empty_like(cl)
+    _lib.fbs_cost_lr(p, left, right, cl, cr, workspace(p, _dev(left)), stream)
+    return cl, cr
+
+
+def lrc(p, disp_left, disp_right, max_diff: int = 0, disp_sub=None, stream=None):
+    """fbs_lrc -> valid uint8 [H][W]; disp_sub (if given) gets -1 where it fails."""
+    import torch
+    from . import _lib
+    valid = torch.empty(disp_left.shape, dtype=torch.uint8, device=disp_left.device)
+    _lib.fbs_lrc(p, disp_left, disp_right, max_diff, valid, disp_sub, stream)
+    return valid
+
+
+def wmf(p, reference, disp_in, stream=None):
+    """fbs_wmf -> int32 [H][W] weighted median of disp_in."""
+    import torch
+    from . import _lib
+    out = torch.empty_like(disp_in)
+    _lib.fbs_wmf(p, reference, disp_in, out, stream)
+    return out

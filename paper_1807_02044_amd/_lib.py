@@ -37,7 +37,8 @@ FBS_PLAN_PER_TILE = 0x2
 # Entry points declared in include/fbs.h (checked by the ABI tests).
 EXPORTS = (
     "fbs_validate", "fbs_workspace_bytes", "fbs_cost", "fbs_aggregate", "fbs_wta_subpixel",
-    "fbs_run", "fbs_run_variant", "fbs_plan_create", "fbs_plan_launch", "fbs_plan_pair_config",
+    "fbs_run", "fbs_run_variant", "fbs_cost_lr", "fbs_lrc", "fbs_lr_workspace_bytes",
+    "fbs_run_lr", "fbs_wmf", "fbs_plan_create", "fbs_plan_launch", "fbs_plan_pair_config",
     "fbs_plan_num_launches", "fbs_plan_destroy", "fbs_surrogate_num_params",
     "fbs_surrogate_create", "fbs_surrogate_destroy", "fbs_surrogate_set_params",
     "fbs_surrogate_get_params", "fbs_surrogate_features", "fbs_surrogate_cheap_run",
@@ -99,8 +100,15 @@ def lib() -> ctypes.CDLL:
         h.fbs_wta_subpixel.argtypes = [P, vp, vp, vp, vp]
         h.fbs_run.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
         h.fbs_run_variant.argtypes = [P]
+        h.fbs_cost_lr.argtypes = [P, vp, vp, vp, vp, vp, vp]
+        h.fbs_lrc.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, vp]
+        h.fbs_lr_workspace_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        h.fbs_run_lr.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
+        h.fbs_wmf.argtypes = [P, vp, vp, vp, vp]
+        h.fbs_wmf.restype = ctypes.c_int
         for f in (h.fbs_validate, h.fbs_workspace_bytes, h.fbs_cost, h.fbs_aggregate,
-                  h.fbs_wta_subpixel, h.fbs_run, h.fbs_run_variant):
+                  h.fbs_wta_subpixel, h.fbs_run, h.fbs_run_variant, h.fbs_cost_lr, h.fbs_lrc,
+                  h.fbs_lr_workspace_bytes, h.fbs_run_lr):
             f.restype = ctypes.c_int
         pp = ctypes.POINTER(ctypes.c_void_p)
         h.fbs_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, P,
@@ -205,6 +213,34 @@ def fbs_wta_subpixel(p, agg, disp, disp_sub, stream=None):
 def fbs_run(p, left, right, disp, disp_sub, agg_out=None, workspace=None, stream=None):
     _check(lib().fbs_run(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(disp), _ptr(disp_sub),
                          _ptr(agg_out), _ptr(workspace), _stream(stream)))
+
+
+def fbs_cost_lr(p, left, right, cost_left, cost_right, workspace=None, stream=None):
+    _check(lib().fbs_cost_lr(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(cost_left),
+                             _ptr(cost_right), _ptr(workspace), _stream(stream)))
+
+
+def fbs_lrc(p, disp_left, disp_right, max_diff, valid, disp_sub, stream=None):
+    _check(lib().fbs_lrc(ctypes.byref(p), _ptr(disp_left), _ptr(disp_right), int(max_diff),
+                         _ptr(valid), _ptr(disp_sub), _stream(stream)))
+
+
+def fbs_lr_workspace_bytes(p: FbsParams) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().fbs_lr_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return int(n.value)
+
+
+def fbs_run_lr(p, left, right, max_diff, disp_left, disp_right, valid, disp_sub, workspace,
+               stream=None):
+    _check(lib().fbs_run_lr(ctypes.byref(p), _ptr(left), _ptr(right), int(max_diff),
+                            _ptr(disp_left), _ptr(disp_right), _ptr(valid), _ptr(disp_sub),
+                            _ptr(workspace), _stream(stream)))
+
+
+def fbs_wmf(p, reference, disp_in, disp_out, stream=None):
+    _check(lib().fbs_wmf(ctypes.byref(p), _ptr(reference), _ptr(disp_in), _ptr(disp_out),
+                         _stream(stream)))
 
 
 def fbs_run_variant(p: FbsParams) -> int:

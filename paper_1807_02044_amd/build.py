@@ -34,8 +34,19 @@ def hipcc() -> str:
     return h
 
 
-def _compile(src: str) -> str:
+def _stale(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    deps = [src, *glob.glob(os.path.join(CSRC, "*.h")),
+            *glob.glob(os.path.join(ROOT, "include", "*.h")), __file__]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not force and not _stale(src, obj):
+        return obj
     cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
@@ -47,12 +58,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8) -> str:
-    """Compile and link libfbs.so; returns its path."""
+def build(jobs: int = 8, force: bool = True) -> str:
+    """Compile and link libfbs.so; returns its path.  force=False recompiles
+    only objects older than their source or any header."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, force), srcs))
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -63,4 +75,4 @@ def build(jobs: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(force="--incremental" not in sys.argv))

@@ -84,6 +84,8 @@ fbs::Geom make_geom(const fbs_params* p)
     g.r = p->radius;
     g.tau = p->cost_cap;
     g.ncc_r = p->ncc_radius;
+    g.gd = p->sigma_s;
+    g.gr = p->sigma_r;
     return g;
 }
 
@@ -106,9 +108,104 @@ size_t ncc_ws_bytes(const fbs_params* p)
 
 bool aligned4(const void* q) { return ((uintptr_t)q & 3u) == 0; }
 
+// Checks of the parameters that a map-only call reads (size and range).
+fbs_status check_map_params(const fbs_params* p)
+{
+    if (!p) return fail(FBS_E_INVALID, "params is NULL");
+    if (p->width < 1 || p->height < 1) return fail(FBS_E_INVALID, "width/height must be >= 1");
+    if (p->width > 65535 || p->height > 65535)
+        return fail(FBS_E_UNSUPPORTED, "width/height above 65535");
+    if (p->d_min < 0 || p->d_max < p->d_min)
+        return fail(FBS_E_INVALID, "need 0 <= d_min <= d_max");
+    if (p->d_max - p->d_min + 1 > FBS_MAX_DISP)
+        return fail(FBS_E_UNSUPPORTED, "more than %d disparities", FBS_MAX_DISP);
+    return FBS_OK;
+}
+
+// The fused path on validated parameters: NCC block sums then the vector-ALU
+// kernel, or TAD on the matrix cores where they apply, else the vector ALUs.
+fbs_status run_fused(const fbs_params* p, const fbs::Geom& g, const uint8_t* left,
+                     const uint8_t* right, int32_t* disp, float* disp_sub, float* agg_out,
+                     int2* stats, hipStream_t s, const char* what)
+{
+    const fbs::Tables t = make_tables(p);
+    if (p->cost_type == FBS_COST_NCC) {
+        fbs_status st = hip_status(fbs::launch_ncc_stats(g, left, right, stats, s), what);
+        if (st != FBS_OK) return st;
+        return hip_status(fbs::launch_valu(g, t, fbs::SRC_NCC, left, right, nullptr, stats, agg_out,
+                                           disp, disp_sub, s),
+                          what);
+    }
+    if (!(p->flags & FBS_F_FORCE_VALU) && fbs::mfma_supported(g))
+        return hip_status(fbs::launch_mfma(g, t, left, right, disp, disp_sub, agg_out, s), what);
+    return hip_status(fbs::launch_valu(g, t, fbs::SRC_TAD, left, right, nullptr, nullptr, agg_out,
+                                       disp, disp_sub, s),
+                      what);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace of the fused left-right path: NCC block sums (NCC only), the two
+// mirrored images, the mirrored right map and the left map.
+struct LrLayout {
+    size_t off_stats, off_lm, off_rm, off_drm, off_dl, total;
+};
+
+LrLayout lr_layout(const fbs_params* p)
+{
+    const size_t n = (size_t)p->width * p->height;
+    const size_t img = align256(n * p->channels);
+    LrLayout l;
+    l.off_stats = 0;
+    l.off_lm = p->cost_type == FBS_COST_NCC ? ncc_ws_bytes(p) : 0;
+    l.off_rm = l.off_lm + img;
+    l.off_drm = l.off_rm + img;
+    l.off_dl = l.off_drm + align256(n * 4);
+    l.total = l.off_dl + align256(n * 4);
+    return l;
+}
+
+// Section II-C on both volumes and Eq. 9, fused: the right-reference run is
+// the left-reference run on the mirrored pair (its map comes out mirrored),
+// then the left run, then the check, which also unmirrors the right map.
+fbs_status run_lr(const fbs_params* p, const uint8_t* left, const uint8_t* right, int max_diff,
+                  int32_t* disp_left, int32_t* disp_right, uint8_t* valid, float* disp_sub,
+                  unsigned char* ws, const LrLayout& lay, hipStream_t s, const char* what)
+{
+    const fbs::Geom g = make_geom(p);
+    int2* stats = (int2*)(ws + lay.off_stats);
+    uint8_t* lm = ws + lay.off_lm;
+    uint8_t* rm = ws + lay.off_rm;
+    int32_t* drm = (int32_t*)(ws + lay.off_drm);
+    int32_t* dl = disp_left ? disp_left : (int32_t*)(ws + lay.off_dl);
+    fbs_status st = hip_status(fbs::launch_mirror(g, left, right, lm, rm, s), what);
+    if (st != FBS_OK) return st;
+    fbs_params pm = *p;
+    pm.row_stride = p->width * p->channels;
+    fbs::Geom gm = make_geom(&pm);
+    st = run_fused(&pm, gm, rm, lm, drm, nullptr, nullptr, stats, s, what);
+    if (st != FBS_OK) return st;
+    st = run_fused(p, g, left, right, dl, disp_sub, nullptr, stats, s, what);
+    if (st != FBS_OK) return st;
+    return hip_status(fbs::launch_lrc(g, dl, drm, true, max_diff, valid, disp_sub, disp_right, s),
+                      what);
+}
+
+
 }  // namespace
 
 namespace fbs {
+// Shared with the no-allocation entry point (fbs_noalloc.hip).
+size_t api_lr_workspace_bytes(const fbs_params* p) { return lr_layout(p).total; }
+fbs_status api_run_lr(const fbs_params* p, const uint8_t* left, const uint8_t* right,
+                      int max_diff, int32_t* disp_left, int32_t* disp_right, uint8_t* valid,
+                      float* disp_sub, unsigned char* ws, hipStream_t s, const char* what)
+{
+    return run_lr(p, left, right, max_diff, disp_left, disp_right, valid, disp_sub, ws,
+                  lr_layout(p), s, what);
+}
+fbs_status api_hip_status(hipError_t e, const char* what) { return hip_status(e, what); }
+bool api_aligned4(const void* q) { return aligned4(q); }
 // Shared with the plan layer (fbs_plan.hip).
 fbs_status api_check_params(const fbs_params* p) { return check_params(p); }
 Geom api_geom(const fbs_params* p) { return make_geom(p); }
@@ -152,11 +249,12 @@ fbs_status fbs_cost(const fbs_params* p, const uint8_t* left, const uint8_t* rig
     const fbs::Geom g = make_geom(p);
     hipStream_t s = (hipStream_t)stream;
     (void)hipGetLastError();
-    if (p->cost_type == FBS_COST_TAD) return hip_status(fbs::launch_cost_tad(g, left, right, cost, s), "fbs_cost");
+    if (p->cost_type == FBS_COST_TAD)
+        return hip_status(fbs::launch_cost_tad(g, left, right, cost, nullptr, s), "fbs_cost");
     int2* stats = (int2*)workspace;
     st = hip_status(fbs::launch_ncc_stats(g, left, right, stats, s), "fbs_cost(stats)");
     if (st != FBS_OK) return st;
-    return hip_status(fbs::launch_cost_ncc(g, left, right, stats, cost, s), "fbs_cost(ncc)");
+    return hip_status(fbs::launch_cost_ncc(g, left, right, stats, cost, nullptr, s), "fbs_cost(ncc)");
 }
 
 fbs_status fbs_aggregate(const fbs_params* p, const uint8_t* left, const float* cost, float* agg,
@@ -219,24 +317,116 @@ fbs_status fbs_run(const fbs_params* p, const uint8_t* left, const uint8_t* righ
     if (workspace && ((uintptr_t)workspace & 15u))
         return fail(FBS_E_INVALID, "workspace must be 16-byte aligned");
     if (!disp && !disp_sub && !agg_out) return FBS_OK;
+    (void)hipGetLastError();
+    return run_fused(p, make_geom(p), left, right, disp, disp_sub, agg_out, (int2*)workspace,
+                     (hipStream_t)stream, "fbs_run");
+}
+
+fbs_status fbs_cost_lr(const fbs_params* p, const uint8_t* left, const uint8_t* right,
+                       float* cost_left, float* cost_right, void* workspace, void* stream)
+{
+    fbs_status st = check_params(p);
+    if (st != FBS_OK) return st;
+    if (!left || !right || !cost_left || !cost_right)
+        return fail(FBS_E_INVALID, "left, right, cost_left and cost_right are required");
+    if (!aligned4(cost_left) || !aligned4(cost_right))
+        return fail(FBS_E_INVALID, "volumes must be 4-byte aligned");
     const fbs::Geom g = make_geom(p);
-    const fbs::Tables t = make_tables(p);
+    const size_t vol = (size_t)g.W * g.H * g.D * sizeof(float);
+    if ((const char*)cost_left < (const char*)cost_right + vol &&
+        (const char*)cost_right < (const char*)cost_left + vol)
+        return fail(FBS_E_INVALID, "cost_left and cost_right overlap");
+    if (p->cost_type == FBS_COST_NCC && !workspace)
+        return fail(FBS_E_WORKSPACE, "NCC cost needs %zu bytes of workspace", ncc_ws_bytes(p));
+    if (workspace && ((uintptr_t)workspace & 15u))
+        return fail(FBS_E_INVALID, "workspace must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     (void)hipGetLastError();
-    if (p->cost_type == FBS_COST_NCC) {
-        int2* stats = (int2*)workspace;
-        st = hip_status(fbs::launch_ncc_stats(g, left, right, stats, s), "fbs_run(stats)");
-        if (st != FBS_OK) return st;
-        return hip_status(fbs::launch_valu(g, t, fbs::SRC_NCC, left, right, nullptr, stats, agg_out,
-                                           disp, disp_sub, s),
-                          "fbs_run(ncc)");
-    }
-    if (!(p->flags & FBS_F_FORCE_VALU) && fbs::mfma_supported(g))
-        return hip_status(fbs::launch_mfma(g, t, left, right, disp, disp_sub, agg_out, s),
-                          "fbs_run(mfma)");
-    return hip_status(fbs::launch_valu(g, t, fbs::SRC_TAD, left, right, nullptr, nullptr, agg_out,
-                                       disp, disp_sub, s),
-                      "fbs_run(valu)");
+    if (p->cost_type == FBS_COST_TAD)
+        return hip_status(fbs::launch_cost_tad(g, left, right, cost_left, cost_right, s),
+                          "fbs_cost_lr");
+    int2* stats = (int2*)workspace;
+    st = hip_status(fbs::launch_ncc_stats(g, left, right, stats, s), "fbs_cost_lr(stats)");
+    if (st != FBS_OK) return st;
+    return hip_status(fbs::launch_cost_ncc(g, left, right, stats, cost_left, cost_right, s),
+                      "fbs_cost_lr(ncc)");
+}
+
+fbs_status fbs_lrc(const fbs_params* p, const int32_t* disp_left, const int32_t* disp_right,
+                   int32_t max_diff, uint8_t* valid, float* disp_sub, void* stream)
+{
+    fbs_status st = check_map_params(p);
+    if (st != FBS_OK) return st;
+    if (!disp_left || !disp_right) return fail(FBS_E_INVALID, "disp_left and disp_right are required");
+    if (max_diff < 0) return fail(FBS_E_INVALID, "max_diff must be >= 0");
+    if (!aligned4(disp_left) || !aligned4(disp_right) || !aligned4(disp_sub))
+        return fail(FBS_E_INVALID, "maps must be 4-byte aligned");
+    if (!valid && !disp_sub) return FBS_OK;
+    (void)hipGetLastError();
+    return hip_status(fbs::launch_lrc(make_geom(p), disp_left, disp_right, false, max_diff, valid,
+                                      disp_sub, nullptr, (hipStream_t)stream),
+                      "fbs_lrc");
+}
+
+fbs_status fbs_lr_workspace_bytes(const fbs_params* p, size_t* bytes)
+{
+    fbs_status st = check_params(p);
+    if (st != FBS_OK) return st;
+    if (!bytes) return fail(FBS_E_INVALID, "bytes is NULL");
+    *bytes = lr_layout(p).total;
+    return FBS_OK;
+}
+
+fbs_status fbs_run_lr(const fbs_params* p, const uint8_t* left, const uint8_t* right,
+                      int32_t max_diff, int32_t* disp_left, int32_t* disp_right, uint8_t* valid,
+                      float* disp_sub, void* workspace, void* stream)
+{
+    fbs_status st = check_params(p);
+    if (st != FBS_OK) return st;
+    if (!left || !right) return fail(FBS_E_INVALID, "left and right are required");
+    if (max_diff < 0) return fail(FBS_E_INVALID, "max_diff must be >= 0");
+    if (!aligned4(disp_left) || !aligned4(disp_right) || !aligned4(disp_sub))
+        return fail(FBS_E_INVALID, "outputs must be 4-byte aligned");
+    const LrLayout lay = lr_layout(p);
+    if (!workspace) return fail(FBS_E_WORKSPACE, "fbs_run_lr needs %zu bytes of workspace", lay.total);
+    if ((uintptr_t)workspace & 255u) return fail(FBS_E_INVALID, "workspace must be 256-byte aligned");
+    if (!disp_left && !disp_right && !valid && !disp_sub) return FBS_OK;
+    (void)hipGetLastError();
+    return run_lr(p, left, right, max_diff, disp_left, disp_right, valid, disp_sub,
+                  (unsigned char*)workspace, lay, (hipStream_t)stream, "fbs_run_lr");
+}
+
+fbs_status fbs_wmf(const fbs_params* p, const uint8_t* reference, const int32_t* disp_in,
+                   int32_t* disp_out, void* stream)
+{
+    if (!p) return fail(FBS_E_INVALID, "params is NULL");
+    if (p->width < 1 || p->height < 1) return fail(FBS_E_INVALID, "width/height must be >= 1");
+    if (p->width > 65535 || p->height > 65535)
+        return fail(FBS_E_UNSUPPORTED, "width/height above 65535");
+    if (p->channels != 1 && p->channels != 3) return fail(FBS_E_INVALID, "channels must be 1 or 3");
+    if ((long long)p->row_stride < (long long)p->width * p->channels)
+        return fail(FBS_E_INVALID, "row_stride %d < width*channels", p->row_stride);
+    if (p->d_min < 0 || p->d_max < p->d_min)
+        return fail(FBS_E_INVALID, "need 0 <= d_min <= d_max");
+    if (p->d_max - p->d_min + 1 > FBS_MAX_DISP)
+        return fail(FBS_E_UNSUPPORTED, "more than %d disparities", FBS_MAX_DISP);
+    if (p->radius < 0) return fail(FBS_E_INVALID, "radius must be >= 0");
+    if (p->radius > FBS_MAX_RADIUS)
+        return fail(FBS_E_UNSUPPORTED, "radius %d above %d", p->radius, FBS_MAX_RADIUS);
+    if (!sigma_ok(p->sigma_s) || !sigma_ok(p->sigma_r))
+        return fail(FBS_E_INVALID, "sigma_s and sigma_r must be > 0");
+    if (!reference || !disp_in || !disp_out)
+        return fail(FBS_E_INVALID, "reference, disp_in and disp_out are required");
+    if (!aligned4(disp_in) || !aligned4(disp_out))
+        return fail(FBS_E_INVALID, "maps must be 4-byte aligned");
+    const size_t map = (size_t)p->width * p->height * 4;
+    if ((const char*)disp_in < (const char*)disp_out + map &&
+        (const char*)disp_out < (const char*)disp_in + map)
+        return fail(FBS_E_INVALID, "disp_in and disp_out overlap");
+    (void)hipGetLastError();
+    return hip_status(fbs::launch_wmf(make_geom(p), make_tables(p), reference, disp_in, disp_out,
+                                      (hipStream_t)stream),
+                      "fbs_wmf");
 }
 
 const char* fbs_status_str(int status)

@@ -19,6 +19,8 @@ struct Geom {
     int r;            // aggregation radius rho
     float tau;        // TAD cap
     int ncc_r;        // NCC block radius varrho
+    float gd, gr;     // gamma_d, gamma_r of Eqs. 7-8 (the matrix-core kernel's
+                      // double-precision recheck of near ties)
 };
 
 // Support-weight factors, computed on the host in double precision and
@@ -35,14 +37,28 @@ struct Tables {
 enum CostSrc { SRC_VOLUME = 0, SRC_TAD = 1, SRC_NCC = 2 };
 
 // ---- launchers (each returns the launch status; no synchronisation) ----
+// cost_r (may be null): the right volume as well, by dual storage
 hipError_t launch_cost_tad(const Geom& g, const uint8_t* L, const uint8_t* R, float* cost,
-                           hipStream_t s);
+                           float* cost_r, hipStream_t s);
 hipError_t launch_ncc_stats(const Geom& g, const uint8_t* L, const uint8_t* R, int2* stats,
                             hipStream_t s);
 hipError_t launch_cost_ncc(const Geom& g, const uint8_t* L, const uint8_t* R,
-                           const int2* stats, float* cost, hipStream_t s);
+                           const int2* stats, float* cost, float* cost_r, hipStream_t s);
+// Both images mirrored left-right into packed copies (row stride W*C).
+hipError_t launch_mirror(const Geom& g, const uint8_t* L, const uint8_t* R, uint8_t* Lm,
+                         uint8_t* Rm, hipStream_t s);
+// Eq. 9 on a left map and a right map (right_mirrored: the right map is
+// stored mirrored, column W-1-u holds u); valid, sub, right_out optional.
+hipError_t launch_lrc(const Geom& g, const int32_t* dl, const int32_t* dr, bool right_mirrored,
+                      int max_diff, uint8_t* valid, float* sub, int32_t* right_out, hipStream_t s);
 hipError_t launch_wta_subpixel(const Geom& g, const float* agg, int32_t* disp, float* sub,
                                hipStream_t s);
+
+// Weighted median filter of an int32 map (g.r = window radius; values
+// outside [g.dmin, g.dmin + g.D - 1] are holes).
+hipError_t launch_wmf(const Geom& g, const Tables& t, const uint8_t* img, const int32_t* din,
+                      int32_t* dout, hipStream_t s);
+int wmf_lds_bytes(int r, int ch);
 
 // Bilateral aggregation on the vector ALUs.  src selects where costs come
 // from (a materialised volume, or TAD / NCC computed in the kernel); agg,

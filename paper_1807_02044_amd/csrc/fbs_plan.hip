@@ -403,6 +403,11 @@ fbs_status fbs_plan_launch(fbs_plan* p, const uint8_t* const* left, const uint8_
     // the previous launch's pointer upload must have left the pinned mirror
     if (hipEventSynchronize(p->copied) != hipSuccess)
         return api_fail(FBS_E_HIP, "plan: event wait failed");
+    // One pointer table and one set of queue counters per plan: this launch
+    // starts on the device only after the previous launch (on any stream)
+    // has finished with them.
+    if (hipStreamWaitEvent(s, p->done, 0) != hipSuccess)
+        return api_fail(FBS_E_HIP, "plan: ordering after the previous launch failed");
     for (int i = 0; i < n; ++i) {
         p->h_ptrs[i] = (void*)left[i];
         p->h_ptrs[n + i] = (void*)right[i];

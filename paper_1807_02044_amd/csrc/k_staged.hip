@@ -1,10 +1,13 @@
 // k_staged.hip - the materialising kernels of the staged path:
 //   cost volume (TAD, or the paper's NCC with pre-computed block sums) and
-//   WTA + subpixel over an aggregated volume.
+//   WTA + subpixel over an aggregated volume; and the small per-pixel
+//   kernels of the left-right path: image mirroring and the consistency
+//   check of Eq. 9.
 //
-// All of them are bound by HBM traffic: each writes or reads 4*W*H*D bytes of
-// float volume once, with lanes along x so every access is a coalesced row
-// segment of the [D][H][W] layout.
+// The cost kernels optionally also write the right volume by dual storage
+// (Section II-A).  All of them are bound by HBM traffic: each writes or reads
+// 4*W*H*D bytes of float volume once, with lanes along x so every access is a
+// coalesced row segment of the [D][H][W] layout.
 #include "fbs_device.h"
 #include "fbs_internal.h"
 
@@ -15,12 +18,27 @@ namespace {
 constexpr int kRowThreads = 256;  // lanes along x per workgroup
 constexpr int kSlab = 16;         // disparities per thread in the cost kernels
 
+// Dual storage of the right volume (Section II-A): the cost computed at left
+// pixel x and disparity d is also the right volume's value at (x - d, d), so
+// a thread that computes it writes it to both volumes.  Right-volume entries
+// whose match x = u + d lies past the right edge have no such thread; the
+// thread at x = u (u >= W - d) writes them with the off-image value.
+__device__ __forceinline__ void store_right(const Geom& g, float* __restrict__ cost_r, size_t plane_k,
+                                            int x, int y, int d, bool computed, float c, float off)
+{
+    float* row = cost_r + plane_k + (size_t)y * g.W;
+    if (computed) row[x - d] = c;
+    if (x >= g.W - d) row[x] = off;
+}
+
 // TAD cost (Section II-A cost step with the truncated absolute difference):
 // C(x,y,d) = min(mean_ch |L - R(x-d)|, tau); tau where x-d is off-image.
+// cost_r (may be null): the right volume, by dual storage.
 template <int CH>
 __global__ __launch_bounds__(kRowThreads) void k_cost_tad(Geom g, const uint8_t* __restrict__ L,
                                                           const uint8_t* __restrict__ R,
-                                                          float* __restrict__ cost)
+                                                          float* __restrict__ cost,
+                                                          float* __restrict__ cost_r)
 {
     const int x = blockIdx.x * kRowThreads + threadIdx.x;
     const int y = blockIdx.y;
@@ -45,6 +63,7 @@ __global__ __launch_bounds__(kRowThreads) void k_cost_tad(Geom g, const uint8_t*
             c = fminf(m, g.tau);
         }
         out[(size_t)k * plane] = c;
+        if (cost_r) store_right(g, cost_r, (size_t)k * plane, x, y, g.dmin + k, xr >= 0, c, g.tau);
     }
 }
 
@@ -74,11 +93,12 @@ __global__ __launch_bounds__(kRowThreads) void k_ncc_stats(Geom g, const uint8_t
 }
 
 // NCC cost 1 - c (Eq. 1): only the cross term sum i_l * i_r is formed here;
-// the block sums come from k_ncc_stats.
+// the block sums come from k_ncc_stats.  cost_r as for k_cost_tad.
 __global__ __launch_bounds__(kRowThreads) void k_cost_ncc(Geom g, const uint8_t* __restrict__ L,
                                                           const uint8_t* __restrict__ R,
                                                           const int2* __restrict__ stats,
-                                                          float* __restrict__ cost)
+                                                          float* __restrict__ cost,
+                                                          float* __restrict__ cost_r)
 {
     const int x = blockIdx.x * kRowThreads + threadIdx.x;
     const int y = blockIdx.y;
@@ -108,6 +128,7 @@ __global__ __launch_bounds__(kRowThreads) void k_cost_ncc(Geom g, const uint8_t*
             c = ncc_cost(n, sl.x, sl.y, sr.x, sr.y, slr);
         }
         out[(size_t)k * plane] = c;
+        if (cost_r) store_right(g, cost_r, (size_t)k * plane, x, y, d, x - d >= 0, c, 2.0f);
     }
 }
 
@@ -133,16 +154,64 @@ __global__ __launch_bounds__(kRowThreads) void k_wta_subpixel(Geom g,
     if (sub) sub[(size_t)y * g.W + x] = ds;
 }
 
+// Left-right mirror of both images into packed copies: column x of the copy
+// is column W-1-x of the image, channels kept in order.  Mirroring turns the
+// right-reference problem (match of right pixel u is left pixel u + d,
+// weights from the right image) into the left-reference one on the mirrored
+// pair (reference = mirrored right image, target = mirrored left image).
+template <int CH>
+__global__ __launch_bounds__(kRowThreads) void k_mirror(Geom g, const uint8_t* __restrict__ L,
+                                                        const uint8_t* __restrict__ R,
+                                                        uint8_t* __restrict__ Lm,
+                                                        uint8_t* __restrict__ Rm)
+{
+    const int x = blockIdx.x * kRowThreads + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= g.W) return;
+    const uint8_t* src = (blockIdx.z ? R : L) + (size_t)y * g.stride + (size_t)(g.W - 1 - x) * CH;
+    uint8_t* dst = (blockIdx.z ? Rm : Lm) + ((size_t)y * g.W + x) * CH;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) dst[c] = src[c];
+}
+
+// Left-right consistency, Eq. 9: left pixel (x, y) with disparity d keeps it
+// when x - d is in the image and the right map holds d there (within
+// max_diff).  Where the check fails the refined map gets -1 (match removed).
+// MIRRORED: the right map is stored mirrored (column W-1-u holds u); it is
+// also written out unmirrored to right_out when that is given.
+template <bool MIRRORED>
+__global__ __launch_bounds__(kRowThreads) void k_lrc(Geom g, const int32_t* __restrict__ dl,
+                                                     const int32_t* __restrict__ dr, int max_diff,
+                                                     uint8_t* __restrict__ valid,
+                                                     float* __restrict__ sub,
+                                                     int32_t* __restrict__ right_out)
+{
+    const int x = blockIdx.x * kRowThreads + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= g.W) return;
+    const size_t row = (size_t)y * g.W;
+    const int d = dl[row + x];
+    const int u = x - d;
+    bool ok = false;
+    if (u >= 0 && u < g.W) {
+        const int diff = dr[row + (MIRRORED ? g.W - 1 - u : u)] - d;
+        ok = diff <= max_diff && -diff <= max_diff;
+    }
+    if (valid) valid[row + x] = ok ? 1 : 0;
+    if (sub && !ok) sub[row + x] = -1.0f;
+    if (right_out) right_out[row + x] = dr[row + (MIRRORED ? g.W - 1 - x : x)];
+}
+
 }  // namespace
 
 hipError_t launch_cost_tad(const Geom& g, const uint8_t* L, const uint8_t* R, float* cost,
-                           hipStream_t s)
+                           float* cost_r, hipStream_t s)
 {
     dim3 grid((g.W + kRowThreads - 1) / kRowThreads, g.H, (g.D + kSlab - 1) / kSlab);
     if (g.C == 3)
-        hipLaunchKernelGGL(k_cost_tad<3>, grid, dim3(kRowThreads), 0, s, g, L, R, cost);
+        hipLaunchKernelGGL(k_cost_tad<3>, grid, dim3(kRowThreads), 0, s, g, L, R, cost, cost_r);
     else
-        hipLaunchKernelGGL(k_cost_tad<1>, grid, dim3(kRowThreads), 0, s, g, L, R, cost);
+        hipLaunchKernelGGL(k_cost_tad<1>, grid, dim3(kRowThreads), 0, s, g, L, R, cost, cost_r);
     return hipGetLastError();
 }
 
@@ -155,10 +224,10 @@ hipError_t launch_ncc_stats(const Geom& g, const uint8_t* L, const uint8_t* R, i
 }
 
 hipError_t launch_cost_ncc(const Geom& g, const uint8_t* L, const uint8_t* R,
-                           const int2* stats, float* cost, hipStream_t s)
+                           const int2* stats, float* cost, float* cost_r, hipStream_t s)
 {
     dim3 grid((g.W + kRowThreads - 1) / kRowThreads, g.H, (g.D + kSlab - 1) / kSlab);
-    hipLaunchKernelGGL(k_cost_ncc, grid, dim3(kRowThreads), 0, s, g, L, R, stats, cost);
+    hipLaunchKernelGGL(k_cost_ncc, grid, dim3(kRowThreads), 0, s, g, L, R, stats, cost, cost_r);
     return hipGetLastError();
 }
 
@@ -167,6 +236,30 @@ hipError_t launch_wta_subpixel(const Geom& g, const float* agg, int32_t* disp, f
 {
     dim3 grid((g.W + kRowThreads - 1) / kRowThreads, g.H);
     hipLaunchKernelGGL(k_wta_subpixel, grid, dim3(kRowThreads), 0, s, g, agg, disp, sub);
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror(const Geom& g, const uint8_t* L, const uint8_t* R, uint8_t* Lm,
+                         uint8_t* Rm, hipStream_t s)
+{
+    dim3 grid((g.W + kRowThreads - 1) / kRowThreads, g.H, 2);
+    if (g.C == 3)
+        hipLaunchKernelGGL(k_mirror<3>, grid, dim3(kRowThreads), 0, s, g, L, R, Lm, Rm);
+    else
+        hipLaunchKernelGGL(k_mirror<1>, grid, dim3(kRowThreads), 0, s, g, L, R, Lm, Rm);
+    return hipGetLastError();
+}
+
+hipError_t launch_lrc(const Geom& g, const int32_t* dl, const int32_t* dr, bool right_mirrored,
+                      int max_diff, uint8_t* valid, float* sub, int32_t* right_out, hipStream_t s)
+{
+    dim3 grid((g.W + kRowThreads - 1) / kRowThreads, g.H);
+    if (right_mirrored)
+        hipLaunchKernelGGL(k_lrc<true>, grid, dim3(kRowThreads), 0, s, g, dl, dr, max_diff, valid,
+                           sub, right_out);
+    else
+        hipLaunchKernelGGL(k_lrc<false>, grid, dim3(kRowThreads), 0, s, g, dl, dr, max_diff, valid,
+                           sub, right_out);
     return hipGetLastError();
 }
 

@@ -198,6 +198,116 @@ __device__ __forceinline__ uint32_t bf16_bits(float f)
 // cost is formed exactly as for agg_out, so the features equal those of
 // fbs_surrogate_features applied to agg_out bit for bit.
 //
+// Double-precision recheck of one pixel of the tile, from the definition:
+// Eq. 6 with the weights of Eqs. 7-8 (exp in double) and the TAD cost from the
+// staged left tile and right strip, WTA (ties to the lowest d) and Eq. 10.
+// All 64 lanes of the wave take part; a pass gives lane l the aggregated
+// costs at disparity indices base + l + 64 j (j < 4).  Every lane returns the
+// pixel's disparity index and subpixel disparity.  Used only where the
+// fp16-split weights cannot order near ties.
+template <int R, int CH>
+__device__ __forceinline__ void recheck_pass(const Geom& g, const uint8_t* s_L, const uint8_t* s_R,
+                                             int LWB, int RWB, int prow, int pcol, int x, int y,
+                                             int base, int lane, double (&a)[4])
+{
+    const int D = g.D, dmax = g.dmin + D - 1;
+    const double igd = 1.0 / ((double)g.gd * (double)g.gd);
+    const double igr = 1.0 / ((double)g.gr * (double)g.gr);
+    const double tau = (double)g.tau;
+    int lp[CH];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(prow + R) * LWB + (pcol + R) * CH + ch];
+    double num[4] = {0.0, 0.0, 0.0, 0.0};
+    double den = 0.0;
+#pragma unroll 1
+    for (int dy = -R; dy <= R; ++dy) {
+        if (y + dy < 0 || y + dy >= g.H) continue;
+        const int row = prow + R + dy;
+#pragma unroll 1
+        for (int dx = -R; dx <= R; ++dx) {
+            const int qx = x + dx;
+            if (qx < 0 || qx >= g.W) continue;
+            const int col = pcol + R + dx;
+            int lq[CH];
+            double d2 = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch) {
+                lq[ch] = s_L[row * LWB + col * CH + ch];
+                const double t = (double)(lq[ch] - lp[ch]);
+                d2 += t * t;
+            }
+            d2 /= (double)CH;
+            const double w = exp(-(double)(dx * dx + dy * dy) * igd) * exp(-d2 * igr);
+            den += w;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = base + lane + 64 * j;
+                if (k >= 0 && k < D) {
+                    const int d = g.dmin + k;
+                    double c = tau;
+                    if (qx - d >= 0) {
+                        int sad = 0;
+#pragma unroll
+                        for (int ch = 0; ch < CH; ++ch)
+                            sad += abs(lq[ch] - (int)s_R[row * RWB + (col + dmax - d) * CH + ch]);
+                        const double m = (double)sad / (double)CH;
+                        c = m < tau ? m : tau;
+                    }
+                    num[j] += w * c;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[j] = num[j] / den;
+}
+
+template <int R, int CH>
+__device__ __forceinline__ void recheck_pixel(const TileJob& job, const uint8_t* s_L, const uint8_t* s_R,
+                                              int LWB, int RWB, int prow, int pcol, int X0, int Y0,
+                                              int lane, int& k_out, float& ds_out)
+{
+    const Geom& g = job.g;
+    const int D = g.D;
+    const int x = X0 + pcol, y = Y0 + prow;
+    // lane-local first minimum over ascending k, pass by pass, then across the wave
+    double bv = 0.0;
+    int bk = -1;
+#pragma unroll 1
+    for (int base = 0; base < D; base += 256) {
+        double a[4];
+        recheck_pass<R, CH>(g, s_L, s_R, LWB, RWB, prow, pcol, x, y, base, lane, a);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = base + lane + 64 * j;
+            if (k < D && (bk < 0 || a[j] < bv)) {
+                bv = a[j];
+                bk = k;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int ok = __shfl_xor(bk, off);
+        if (ok >= 0 && (bk < 0 || ov < bv || (ov == bv && ok < bk))) {
+            bv = ov;
+            bk = ok;
+        }
+    }
+    // the aggregated costs at bk - 1 (lane 0) and bk + 1 (lane 2) for Eq. 10
+    double ds = (double)(g.dmin + bk);
+    if (bk > 0 && bk < D - 1) {
+        double a[4];
+        recheck_pass<R, CH>(g, s_L, s_R, LWB, RWB, prow, pcol, x, y, bk - 1, lane, a);
+        const double cm = __shfl(a[0], 0), cp = __shfl(a[0], 2);
+        const double dnm = 2.0 * cm + 2.0 * cp - 4.0 * bv;
+        if (dnm > 0.0) ds += (cm - cp) / dnm;
+    }
+    k_out = bk;
+    ds_out = (float)ds;
+}
+
 // CO (chunk-outer): the whole disparity range sits in one LDS slab (nb equal to
 // the number of 16-disparity blocks, at most kCoMax); each K chunk's weights
 // are formed and immediately applied to every block, so only one chunk of
@@ -393,6 +503,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     // ---- running WTA over this lane's quarter of the disparity range ----
     const float kInf = __builtin_inff();
     float best = kInf, cm = kInf, cp = kInf, prev = kInf, first_v = kInf, last_v = kInf;
+    float best2 = kInf;  // second-lowest value of this lane's quarter (near-tie check)
     int bi = -1;
     bool need_cp = false;
     // FEAT: this lane's 8 lowest aggregated costs of its quarter, ascending,
@@ -520,11 +631,13 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
                 last_v = v;
                 const bool lt = v < best;
                 if (lt) {
+                    best2 = best;
                     cm = prev;
                     best = v;
                     bi = k;
-                } else if (need_cp) {
-                    cp = v;
+                } else {
+                    if (need_cp) cp = v;
+                    best2 = fminf(best2, v);
                 }
                 need_cp = lt;
                 prev = v;
@@ -660,10 +773,15 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     int wk = __shfl(bi, n), wc = __shfl((int)need_cp, n), wt = 0;
     float left_last = kInf;   // last value of the quarter before the winner
     float prev_last = __shfl(last_v, n);
+    float qb[4], qs[4];       // each quarter's lowest and second-lowest value
+    qb[0] = wv;
+    qs[0] = __shfl(best2, n);
 #pragma unroll
     for (int t = 1; t < 4; ++t) {
         const int src = n + 16 * t;
         const float tv = __shfl(best, src);
+        qb[t] = tv;
+        qs[t] = __shfl(best2, src);
         const int tk = __shfl(bi, src);
         const float tm = __shfl(cm, src), tp = __shfl(cp, src);
         const int tc = __shfl((int)need_cp, src);
@@ -676,11 +794,44 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int ti
     }
     // first value of the quarter after the winner
     const float right_first = __shfl(first_v, n + 16 * min(wt + 1, 3));
+    // Near ties the weights' resolution cannot order.  Each weight below the
+    // fp16 range of the split (w < 2^-38) is lost, so every numerator carries
+    // an absolute error up to T * cap * 2^-25 (scaled units) besides its
+    // relative 2^-22.  Where the lowest value is small enough that this
+    // absolute error could exceed the 1e-5 relative tie zone, and the second
+    // lowest lies within that error of it, the pixel is recomputed below in
+    // double precision from the definition.
+    float second = kInf;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) second = fminf(second, t == wt ? qs[t] : qb[t]);
+    constexpr float kTaps = (float)((2 * R + 1) * (2 * R + 1));
+    const float abs_err = kTaps * scap * 0x1.0p-25f;
+    const bool unsafe = pin && wv < kTaps * scap * 6e-3f &&
+                        !(second - wv >= 4.0f * abs_err + 1e-6f * second);
+    uint64_t recheck = __ballot(gq == 0 && unsafe);
+    int fix_k = -1;
+    float fix_ds = 0.0f;
+    while (recheck) {
+        const int n0 = __builtin_ctzll(recheck);
+        recheck &= recheck - 1;
+        int rk;
+        float rds;
+        recheck_pixel<R, CH>(job, s_L, s_R, LWB, RWB, grow0 + n0 / GW, gcol0 + n0 % GW, X0, Y0,
+                             lane, rk, rds);
+        if (lane == n0) {
+            fix_k = rk;
+            fix_ds = rds;
+        }
+    }
     if (gq == 0 && pin) {
         float fm = wm, fp = wp;
         if (wk == wt * Q && wt > 0) fm = left_last;
         if (wc && wt < 3 && wk + 1 < D) fp = right_first;
-        const float ds = eq10_subpixel(g.dmin + wk, wk > 0 && wk < D - 1, fm, wv, fp);
+        float ds = eq10_subpixel(g.dmin + wk, wk > 0 && wk < D - 1, fm, wv, fp);
+        if (fix_k >= 0) {
+            wk = fix_k;
+            ds = fix_ds;
+        }
         const size_t o = (size_t)py * g.W + px;
         if (disp) disp[o] = g.dmin + wk;
         if (sub) sub[o] = ds;

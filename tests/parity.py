@@ -17,6 +17,12 @@
   a = A(d*-1) - A(d*) and b = A(d*+1) - A(d*), so a pixel whose parabola is
   flat, (a + b) < 4e-3 * A(d*) + 2000 * floor, may miss; every such violator is counted and
   returned, and a violator outside that zone fails.
+
+The absolute floor is accounted for separately: ``disp_tie_floor`` counts the
+pixels whose integer disparity is accepted only because of the floor (outside
+the purely relative 1e-5 tie zone), ``sub_flat_floor`` the subpixel misses
+excused only by the floor's share of the flat zone.  Both must be zero for a
+report to pass, so the floor is never what decides a pixel.
 """
 from __future__ import annotations
 
@@ -43,20 +49,24 @@ class Report:
     n: int = 0
     disp_equal: int = 0
     disp_tie: int = 0
+    disp_tie_floor: int = 0
     disp_bad: int = 0
     sub_bad: int = 0
     sub_flat: int = 0
+    sub_flat_floor: int = 0
     agg_bad: int = 0
     agg_max_rel: float = 0.0
     notes: List[str] = field(default_factory=list)
 
     @property
     def ok(self) -> bool:
-        return self.disp_bad == 0 and self.sub_bad == 0 and self.agg_bad == 0
+        return (self.disp_bad == 0 and self.sub_bad == 0 and self.agg_bad == 0
+                and self.disp_tie_floor == 0 and self.sub_flat_floor == 0)
 
     def __str__(self):
         return (f"n={self.n} disp_equal={self.disp_equal} tie={self.disp_tie} "
-                f"disp_bad={self.disp_bad} sub_bad={self.sub_bad} sub_flat={self.sub_flat} "
+                f"tie_floor={self.disp_tie_floor} disp_bad={self.disp_bad} sub_bad={self.sub_bad} "
+                f"sub_flat={self.sub_flat} sub_flat_floor={self.sub_flat_floor} "
                 f"agg_bad={self.agg_bad} agg_max_rel={self.agg_max_rel:.3g} "
                 + "; ".join(self.notes[:5]))
 
@@ -97,10 +107,17 @@ def compare_maps(disp_gpu, sub_gpu, disp_o, sub_o, agg_o_pd: np.ndarray, d_min: 
     ag = A[dg - d_min, idx]
     ao = A[do - d_min, idx]
     eq = dg == do
-    tie = (~eq) & (ag - ao <= TIE_RTOL * np.maximum(np.abs(ag), np.abs(ao)) + floor)
+    rel_gap = TIE_RTOL * np.maximum(np.abs(ag), np.abs(ao))
+    tie = (~eq) & (ag - ao <= rel_gap + floor)
+    tie_rel = (~eq) & (ag - ao <= rel_gap + TIE_ATOL)
     bad = (~eq) & (~tie)
     rep.disp_equal += int(eq.sum())
     rep.disp_tie += int(tie.sum())
+    rep.disp_tie_floor += int((tie & ~tie_rel).sum())
+    if (tie & ~tie_rel).any():
+        i = int(np.argwhere(tie & ~tie_rel)[0][0])
+        rep.notes.append(f"tie only by the floor at {i}: gpu={dg[i]} oracle={do[i]} "
+                         f"A_o(gpu)={ag[i]!r} A_o(oracle)={ao[i]!r}")
     rep.disp_bad += int(bad.sum())
     if bad.any():
         i = int(np.argwhere(bad)[0][0])
@@ -118,7 +135,9 @@ def compare_maps(disp_gpu, sub_gpu, disp_o, sub_o, agg_o_pd: np.ndarray, d_min: 
         b = A[kp, idx] - c0
         # with the absolute floor as cost error, 2 * eps / (a + b) > 1e-3 px
         flat = (a + b) < FLAT_ZONE * np.abs(c0) + 2e3 * floor
+        flat_rel = (a + b) < FLAT_ZONE * np.abs(c0) + 2e3 * TIE_ATOL
         rep.sub_flat += int((viol & flat).sum())
+        rep.sub_flat_floor += int((viol & flat & ~flat_rel).sum())
         hard = viol & ~flat
         rep.sub_bad += int(hard.sum())
         if hard.any():

@@ -197,3 +197,68 @@ def test_plan_class_mixing_slab_depths(tmp_path):
             np.testing.assert_array_equal(Ds[i], d.cpu().numpy(), err_msg=wl.name)
             np.testing.assert_array_equal(Ss[i].view(np.uint32), s.cpu().numpy().view(np.uint32))
         plan.close()
+
+
+def test_one_plan_launched_on_two_streams():
+    """Two launches of one plan on two streams, with different buffers: the
+    second waits for the first on the device, so both equal fbs_run."""
+    pairs = _batch()
+    params = [fbs.params_for(wl) for wl, _ in pairs]
+    plan = L.FbsPlan(params)
+    dev = torch.device("cuda:0")
+    Ls = [torch.from_numpy(p.left).to(dev) for _, p in pairs]
+    Rs = [torch.from_numpy(p.right).to(dev) for _, p in pairs]
+    outs = []
+    for _ in range(2):
+        outs.append(([torch.full((wl.height, wl.width), -1, dtype=torch.int32, device=dev)
+                      for wl, _ in pairs],
+                     [torch.full((wl.height, wl.width), -1.0, dtype=torch.float32, device=dev)
+                      for wl, _ in pairs]))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for k in range(2):
+            plan.launch(Ls, Rs, outs[k][0], outs[k][1], streams[k])
+    torch.cuda.synchronize()
+    for i, (wl, pr) in enumerate(pairs):
+        d_ref, s_ref = fbs.run(params[i], Ls[i], Rs[i])
+        d_ref, s_ref = d_ref.cpu().numpy(), s_ref.cpu().numpy()
+        for k in range(2):
+            np.testing.assert_array_equal(outs[k][0][i].cpu().numpy(), d_ref)
+            np.testing.assert_array_equal(outs[k][1][i].cpu().numpy().view(np.uint32),
+                                          s_ref.view(np.uint32))
+    plan.close()
+
+
+# pair shapes of the 64-pair batch at their real sizes: the largest frame with
+# the largest range and radius, a mid one, and a small one
+BIG = [(1280, 960, 0, 127, 10), (960, 720, 0, 95, 5), (320, 240, 0, 31, 7)]
+
+
+@pytest.mark.parametrize("per_tile", [False, True])
+def test_batch_sized_pairs_vs_oracle_sampled(per_tile):
+    pairs = []
+    for i, (W, H, d0, d1, r) in enumerate(BIG):
+        wl = scenes.Workload(f"big{i}", W, H, 1, d0, d1, r, float(r), 10.0, 40.0,
+                             scene="slanted", seed=1000 + 7 * i, n_planes=8)
+        pairs.append((wl, scenes.make_pair(wl)))
+    params = [fbs.params_for(wl) for wl, _ in pairs]
+    plan = L.FbsPlan(params, per_tile=per_tile)
+    _say("batch-sized pairs, per_tile", per_tile,
+         [plan.pair_config(i) for i in range(len(pairs))])
+    Ls, Rs, Ds, Ss = _run_plan(plan, pairs)
+    plan.close()
+    for i, (wl, pr) in enumerate(pairs):
+        d_ref, s_ref = fbs.run(params[i], Ls[i], Rs[i])
+        np.testing.assert_array_equal(Ds[i], d_ref.cpu().numpy())
+        np.testing.assert_array_equal(Ss[i].view(np.uint32), s_ref.cpu().numpy().view(np.uint32))
+        rng = np.random.default_rng(40 + i)
+        xs = np.concatenate([rng.integers(0, wl.width, 300), [0, wl.width - 1, wl.width // 2]])
+        ys = np.concatenate([rng.integers(0, wl.height, 300), [wl.height - 1, 0, wl.height // 2]])
+        xs, ys = xs.astype(np.int32), ys.astype(np.int32)
+        pb = Problem.from_workload(wl)
+        ao, do, so = oracle.fbs_pixels(pb, pr.left, pr.right, xs, ys)
+        rep = compare_maps(Ds[i][ys, xs], Ss[i][ys, xs], do, so, ao.T, pb.d_min,
+                           floor=weight_floor((2 * pb.radius + 1) ** 2, pb.tau))
+        _say(wl.name, wl.width, wl.height, wl.n_disp, wl.radius, rep)
+        assert rep.ok, f"{wl.name}: {rep}"

@@ -1,0 +1,123 @@
+"""Weighted median filter (fbs_wmf) against the FP64 oracle.
+
+Integer output: equal to the oracle's, or - where float32 sums decide a
+near tie - a value that the oracle's own cumulative weights place within a
+relative 1e-5 of the half-total crossing (below < half (1 + 1e-5) and
+upto >= half (1 - 1e-5)); such pixels are counted.  With uniform weights
+every sum is an exact small integer, so the outputs must be equal bit for
+bit."""
+import math
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Problem
+from paper_1807_02044_amd import _lib as L
+from paper_1807_02044_amd import scenes
+import paper_1807_02044_amd as fbs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _d(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _check(pb, img, din, got):
+    want = oracle.wmf(pb, img, din)
+    diff = got != want
+    n_tie = 0
+    if diff.any():
+        below, upto, total = oracle.wmf_cumulative(pb, img, din, got)
+        half = 0.5 * total
+        ok = (got >= 0) & (below < half * (1 + TOL)) & (upto >= half * (1 - TOL))
+        bad = diff & ~ok
+        assert not bad.any(), (np.argwhere(bad)[:3], got[bad][:3], want[bad][:3])
+        n_tie = int(diff.sum())
+    print(f"wmf {img.shape} r={pb.radius}: {n_tie} near-tie pixels of {got.size}", flush=True)
+    return n_tie
+
+
+def _params(img, pb):
+    H, W = img.shape[:2]
+    C = 1 if img.ndim == 2 else 3
+    return L.make_params(W, H, C, pb.d_min, pb.d_max, pb.radius, pb.gamma_d, pb.gamma_r, 40.0)
+
+
+CASES = {
+    "gray_r3": dict(W=53, H=37, C=1, dmin=0, dmax=20, r=3, g=(3.0, 10.0)),
+    "rgb_r2": dict(W=41, H=29, C=3, dmin=2, dmax=30, r=2, g=(2.0, 12.0)),
+    "gray_r0": dict(W=20, H=9, C=1, dmin=0, dmax=9, r=0, g=(1.0, 10.0)),
+    "gray_r16": dict(W=45, H=40, C=1, dmin=0, dmax=7, r=16, g=(10.0, 20.0)),
+    "three_levels_D1024": dict(W=70, H=12, C=1, dmin=0, dmax=1023, r=2, g=(3.0, 10.0)),
+    "one_value_range": dict(W=30, H=20, C=1, dmin=5, dmax=5, r=2, g=(3.0, 10.0)),
+    "ragged_rgb_r5": dict(W=37, H=23, C=3, dmin=0, dmax=100, r=5, g=(5.0, 15.0)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_wmf_random_maps_vs_oracle(name):
+    e = CASES[name]
+    rng = np.random.default_rng(zlib.crc32(name.encode()) % 10000)
+    shape = (e["H"], e["W"]) if e["C"] == 1 else (e["H"], e["W"], 3)
+    img = rng.integers(0, 256, shape, dtype=np.uint8)
+    din = rng.integers(e["dmin"] - 2, e["dmax"] + 3, (e["H"], e["W"])).astype(np.int32)
+    din[rng.random((e["H"], e["W"])) < 0.15] = -1
+    pb = Problem(e["dmin"], e["dmax"], e["r"], *e["g"])
+    got = fbs.wmf(_params(img, pb), _d(img), _d(din)).cpu().numpy()
+    _check(pb, img, din, got)
+
+
+@pytest.mark.parametrize("channels", [1, 3])
+def test_wmf_uniform_weights_bit_exact(channels):
+    rng = np.random.default_rng(5 + channels)
+    shape = (31, 44) if channels == 1 else (31, 44, 3)
+    img = rng.integers(0, 256, shape, dtype=np.uint8)
+    din = rng.integers(0, 40, (31, 44)).astype(np.int32)
+    din[rng.random((31, 44)) < 0.3] = -1
+    pb = Problem(0, 39, 4, math.inf, math.inf)
+    got = fbs.wmf(_params(img, pb), _d(img), _d(din)).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.wmf(pb, img, din))
+
+
+def test_wmf_fills_the_checked_map():
+    """The filter on the left-right path's output: holes left by Eq. 9 are
+    filled from their neighbours, compared with the oracle on the same input."""
+    wl = scenes.workload("mid")
+    pr = scenes.make_pair(wl)
+    p = fbs.params_for(wl)
+    Ld, Rd = _d(pr.left), _d(pr.right)
+    dl, dr, valid, sub = fbs.run_lr(p, Ld, Rd, 0)
+    din = torch.where(valid.bool(), dl, torch.full_like(dl, -1))
+    pw = L.make_params(wl.width, wl.height, 1, wl.d_min, wl.d_max, 3, 3.0, 10.0, 40.0)
+    got = fbs.wmf(pw, Ld, din).cpu().numpy()
+    din_h = din.cpu().numpy()
+    pb = Problem(wl.d_min, wl.d_max, 3, 3.0, 10.0)
+    n_tie = _check(pb, pr.left, din_h, got)
+    assert n_tie <= got.size // 1000
+    holes = din_h < 0
+    assert (got[holes] >= 0).mean() > 0.9   # nearly every removed match is refilled
+
+
+def test_wmf_rejects_overlap_and_bad_radius():
+    img = torch.zeros((8, 8), dtype=torch.uint8, device="cuda")
+    m = torch.zeros((8, 8), dtype=torch.int32, device="cuda")
+    p = L.make_params(8, 8, 1, 0, 7, 2, 3.0, 10.0)
+    with pytest.raises(L.FbsError) as e:
+        L.fbs_wmf(p, img, m, m)
+    assert e.value.status == L.FBS_E_INVALID
+    p.radius = 17
+    with pytest.raises(L.FbsError) as e:
+        L.fbs_wmf(p, img, m, torch.empty_like(m))
+    assert e.value.status == L.FBS_E_UNSUPPORTED

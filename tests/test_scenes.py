@@ -56,3 +56,36 @@ def test_batched_mix():
     assert {w.n_disp for w in b} <= {32, 64, 96, 128}
     assert {w.radius for w in b} <= {5, 7, 10}
     assert len({(w.width, w.height) for w in b}) >= 4
+
+
+# ------------------------------------------------ e_PEP of Eqs. 11-12 (sweeps)
+
+def test_pep_hand_worked():
+    from paper_1807_02044_amd import sweeps
+    est = np.array([[1.0, 5.0], [3.0, -1.0]])
+    gt = np.array([[1.0, 2.0], [0.5, 3.0]])
+    # |1-1|=0 ok; |5-2|=3 > 2 error; |3-0.5|=2.5 error; -1 = no estimate, error
+    assert sweeps.pep(est, gt, np.ones((2, 2), bool)) == 75.0
+    # only the first row: one error of two
+    assert sweeps.pep(est, gt, np.array([[1, 1], [0, 0]], bool)) == 50.0
+    # delta is 0 at exactly eps_d (Eq. 12: d <= eps_d)
+    assert sweeps.pep(np.array([4.0]), np.array([2.0]), np.array([True])) == 0.0
+    assert sweeps.pep(np.array([4.0 + 1e-9]), np.array([2.0]), np.array([True])) == 100.0
+    assert sweeps.pep(est, gt, np.zeros((2, 2), bool)) == 0.0
+
+
+def test_region_masks_hand_worked():
+    from paper_1807_02044_amd import sweeps
+    flat = np.full((6, 8), 77, dtype=np.uint8)
+    assert sweeps.textureless(flat).all()
+    ramp = np.tile((np.arange(8) * 10).astype(np.uint8), (6, 1))  # gradient 10 per px
+    tl = sweeps.textureless(ramp)
+    assert not tl[:, 2:-2].any()
+    gt = np.zeros((5, 12))
+    gt[:, 6:] = 10.0                     # a jump between columns 5 and 6
+    m = sweeps.discontinuities(gt)
+    # columns 5 and 6 touch the jump; 2 px either side are inside the band
+    assert m[:, 3:9].all() and not m[:, :3].any() and not m[:, 9:].any()
+    small = gt.copy()
+    small[:, 6:] = 2.0                   # a jump of exactly 2 is not a discontinuity
+    assert not sweeps.discontinuities(small).any()
