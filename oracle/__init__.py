@@ -21,6 +21,8 @@ Bilateral Stereo"):
 * :func:`lrc`           Section II-D, Eq. (9): left-right consistency of two maps
 * :func:`fbs_lrc`       both maps, Eq. (9), and Eq. (10) on the surviving left pixels
 * :func:`wmf`           weighted median filter of a disparity map (Section II-D)
+* :func:`guided_ranges` per-tile search ranges from reliable seeds (Section V)
+* :func:`fbs_ranged`    WTA and Eq. (10) restricted to each tile's range
 * :func:`wmf_cumulative`  window weights below / up to a candidate median
 """
 from __future__ import annotations
@@ -113,11 +115,14 @@ def lib() -> ctypes.CDLL:
         h.orc_lrc.argtypes = [P, i32, i32, ctypes.c_int32, u8p]
         h.orc_fbs_lrc.argtypes = [P, u8, u8, ctypes.c_int32, i32, i32, u8p, f64]
         h.orc_wmf.argtypes = [P, u8, i32, i32]
+        h.orc_guided_ranges.argtypes = [P, i32, u8p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, i32]
+        h.orc_fbs_ranged.argtypes = [P, u8, u8, ctypes.c_int32, ctypes.c_int32, i32, i32, f64]
         h.orc_wmf_cumulative.argtypes = [P, u8, i32, i32, f64, f64, f64]
         for f in (h.orc_cost, h.orc_weights, h.orc_aggregate, h.orc_wta_subpixel, h.orc_fbs,
                   h.orc_fbs_pixels, h.orc_threads, h.orc_cost_right, h.orc_fbs_right,
                   h.orc_fbs_right_pixels, h.orc_lrc, h.orc_fbs_lrc, h.orc_wmf,
-                  h.orc_wmf_cumulative):
+                  h.orc_wmf_cumulative, h.orc_guided_ranges, h.orc_fbs_ranged):
             f.restype = ctypes.c_int
         _lib_handle = h
     return _lib_handle
@@ -357,3 +362,37 @@ def wmf_cumulative(pb: Problem, image: np.ndarray, disp_in: np.ndarray, m: np.nd
     _check(lib().orc_wmf_cumulative(ctypes.byref(_params(pb, img)), _u8(img), _i32(din), _i32(mm),
                                     _f64(below), _f64(upto), _f64(total)), "wmf_cumulative")
     return below, upto, total
+
+
+# ------------------------------------------------- guided search range (Sec. V)
+
+
+def guided_ranges(pb: Problem, disp: np.ndarray, valid: np.ndarray, tile_w: int, tile_h: int,
+                  halo: int, margin: int) -> np.ndarray:
+    """Per-tile (lo, hi) ranges [tiles_y][tiles_x][2] from reliable seeds."""
+    d = np.ascontiguousarray(disp, dtype=np.int32)
+    v = np.ascontiguousarray(valid, dtype=np.uint8)
+    H, W = d.shape
+    ty, tx = (H + tile_h - 1) // tile_h, (W + tile_w - 1) // tile_w
+    out = np.empty((ty, tx, 2), dtype=np.int32)
+    fake = np.zeros((H, W), dtype=np.uint8)
+    _check(lib().orc_guided_ranges(ctypes.byref(_params(pb, fake)), _i32(d),
+                                   v.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), tile_w,
+                                   tile_h, halo, margin, _i32(out)), "guided_ranges")
+    return out
+
+
+def fbs_ranged(pb: Problem, left: np.ndarray, right: np.ndarray, tile_w: int, tile_h: int,
+               ranges: np.ndarray):
+    """(disp, disp_sub) with WTA and Eq. (10) over each tile's range only."""
+    L = np.ascontiguousarray(left)
+    R = np.ascontiguousarray(right)
+    H, W, _ = _shape(L)
+    rg = np.ascontiguousarray(ranges, dtype=np.int32)
+    if rg.shape != ((H + tile_h - 1) // tile_h, (W + tile_w - 1) // tile_w, 2):
+        raise ValueError("ranges must be [tiles_y][tiles_x][2]")
+    disp = np.empty((H, W), dtype=np.int32)
+    sub = np.empty((H, W), dtype=np.float64)
+    _check(lib().orc_fbs_ranged(ctypes.byref(_params(pb, L)), _u8(L), _u8(R), tile_w, tile_h,
+                                _i32(rg), _i32(disp), _f64(sub)), "fbs_ranged")
+    return disp, sub

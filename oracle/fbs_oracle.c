@@ -52,6 +52,16 @@
  * cumulative weight (the weights of values <= m) reaches half of the
  * window's total weight.
  *
+ * Guided search range (Section V, future work): reliable pixels suggest the
+ * search range of their neighbourhood, and only that range is searched.
+ * Reading: the image is cut into tiles of tile_w x tile_h pixels; a tile's
+ * range is [min - margin, max + margin] (clipped to [d_min, d_max]) of the
+ * disparities of the reliable seeds in the tile grown by `halo` pixels on
+ * every side, or the whole range where there is none; each pixel then takes
+ * WTA (Section II-C) and Eq. (10) over its tile's range only, on the same
+ * aggregated costs as the full search - Eq. (10) falls back to d* at the ends
+ * of the tile's range.
+ *
  * Volumes are [D][H][W] with index d - d_min; weights are [H][W][(2r+1)^2]
  * in row-major tap order (dy outer, dx inner).  Images are HWC uint8 with a
  * row stride in bytes.
@@ -445,6 +455,74 @@ int orc_fbs_right_pixels(const orc_params* p, const uint8_t* L, const uint8_t* R
 }
 
 /* Number of OpenMP threads the oracle runs on. */
+/* Per-tile search ranges from reliable seeds (see the header): ranges is
+ * [tiles_y][tiles_x][2] int32 (lo, hi); a seed is a pixel with valid != 0 and
+ * disp within [d_min, d_max]. */
+int orc_guided_ranges(const orc_params* p, const int32_t* disp, const uint8_t* valid,
+                      int32_t tile_w, int32_t tile_h, int32_t halo, int32_t margin,
+                      int32_t* ranges)
+{
+    if (orc_check_filter(p) || tile_w < 1 || tile_h < 1 || halo < 0 || margin < 0) return -1;
+    const int W = p->width, H = p->height;
+    const int tx_n = (W + tile_w - 1) / tile_w, ty_n = (H + tile_h - 1) / tile_h;
+    for (int ty = 0; ty < ty_n; ++ty)
+        for (int tx = 0; tx < tx_n; ++tx) {
+            int lo = p->d_max + 1, hi = p->d_min - 1;
+            for (int y = ty * tile_h - halo; y < (ty + 1) * tile_h + halo; ++y)
+                for (int x = tx * tile_w - halo; x < (tx + 1) * tile_w + halo; ++x) {
+                    if (x < 0 || x >= W || y < 0 || y >= H) continue;
+                    const size_t o = (size_t)y * W + x;
+                    const int d = disp[o];
+                    if (!valid[o] || d < p->d_min || d > p->d_max) continue;
+                    if (d < lo) lo = d;
+                    if (d > hi) hi = d;
+                }
+            int32_t* r = ranges + 2 * ((size_t)ty * tx_n + tx);
+            if (lo > hi) {
+                r[0] = p->d_min;
+                r[1] = p->d_max;
+            } else {
+                r[0] = lo - margin < p->d_min ? p->d_min : lo - margin;
+                r[1] = hi + margin > p->d_max ? p->d_max : hi + margin;
+            }
+        }
+    return 0;
+}
+
+/* The four steps with each pixel's WTA and Eq. (10) restricted to its tile's
+ * range (ranges as for orc_guided_ranges); aggregated costs as orc_fbs. */
+int orc_fbs_ranged(const orc_params* p, const uint8_t* L, const uint8_t* R, int32_t tile_w,
+                   int32_t tile_h, const int32_t* ranges, int32_t* disp, double* disp_sub)
+{
+    if (orc_check(p) || tile_w < 1 || tile_h < 1) return -1;
+    const int W = p->width, H = p->height;
+    const size_t N = (size_t)W * H;
+    const int D = p->d_max - p->d_min + 1;
+    const int tx_n = (W + tile_w - 1) / tile_w;
+    double* agg = (double*)malloc(N * D * sizeof(double));
+    int32_t* tmp = (int32_t*)malloc(N * sizeof(int32_t));
+    double* tsub = (double*)malloc(N * sizeof(double));
+    int rc = (agg && tmp && tsub) ? 0 : -2;
+    if (!rc) rc = orc_fbs(p, L, R, tmp, tsub, agg);
+    for (int y = 0; y < H && !rc; ++y)
+        for (int x = 0; x < W; ++x) {
+            const int32_t* r = ranges + 2 * ((size_t)(y / tile_h) * tx_n + x / tile_w);
+            if (r[0] < p->d_min || r[1] > p->d_max || r[0] > r[1]) {
+                rc = -1;
+                break;
+            }
+            orc_params q = *p;
+            q.d_min = r[0];
+            q.d_max = r[1];
+            const size_t o = (size_t)y * W + x;
+            wta_subpixel_one(&q, agg + (size_t)(r[0] - p->d_min) * N + o, N, disp + o, disp_sub + o);
+        }
+    free(agg);
+    free(tmp);
+    free(tsub);
+    return rc;
+}
+
 typedef struct {
     int32_t value;
     double weight;

@@ -670,3 +670,74 @@ def test_wmf_cumulative_brackets_the_median():
     assert np.all(below < 0.5 * total) and np.all(upto >= 0.5 * total)
     b2, u2, _ = oracle.wmf_cumulative(pb, img, d, m - 1)
     assert np.all(u2 < 0.5 * total)
+
+
+# ------------------------------------- f2: search range from reliable seeds (V)
+
+
+def test_guided_ranges_hand_worked():
+    d = np.array([[5, 5, 9, 9],
+                  [5, 7, 9, 30],
+                  [2, 2, 2, 2]], dtype=np.int32)
+    v = np.array([[1, 1, 1, 1],
+                  [1, 0, 1, 1],
+                  [0, 0, 0, 0]], dtype=np.uint8)
+    pb = Problem(0, 20, 1, 1.0, 1.0)                     # 30 is out of range: no seed
+    r = oracle.guided_ranges(pb, d, v, 2, 2, 0, 1)
+    assert r.shape == (2, 2, 2)
+    assert r[0, 0].tolist() == [4, 6]                     # seeds 5, 5, 5 (7 is not valid)
+    assert r[0, 1].tolist() == [8, 10]                    # seeds 9, 9, 9
+    assert r[1, 0].tolist() == [0, 20]                    # no seed: whole range
+    assert r[1, 1].tolist() == [0, 20]
+    # a halo of one pixel lets the top-left tile see the 9s of its neighbour
+    r = oracle.guided_ranges(pb, d, v, 2, 2, 1, 0)
+    assert r[0, 0].tolist() == [5, 9]
+    # margins clip at the ends of the range
+    r = oracle.guided_ranges(Problem(4, 9, 1, 1.0, 1.0), d, v, 2, 2, 0, 3)
+    assert r[0, 0].tolist() == [4, 8] and r[0, 1].tolist() == [6, 9]
+
+
+def test_ranged_full_ranges_equal_plain():
+    wl = scenes.workload("tiny")
+    pr = scenes.make_pair(wl)
+    pb = Problem.from_workload(wl)
+    d0, s0 = oracle.fbs(pb, pr.left, pr.right)
+    tw, th = 16, 8
+    rg = np.zeros(((wl.height + th - 1) // th, (wl.width + tw - 1) // tw, 2), np.int32)
+    rg[..., 0], rg[..., 1] = pb.d_min, pb.d_max
+    d1, s1 = oracle.fbs_ranged(pb, pr.left, pr.right, tw, th, rg)
+    np.testing.assert_array_equal(d1, d0)
+    np.testing.assert_array_equal(s1, s0)
+
+
+def test_ranged_containing_the_minimum_keeps_it():
+    """Ranges built from the full result's own disparities (with a margin of
+    one) contain every pixel's first minimum with a neighbour on each side,
+    so the restricted search returns the full search's result."""
+    wl = scenes.workload("tiny")
+    pr = scenes.make_pair(wl)
+    pb = Problem.from_workload(wl)
+    d0, s0 = oracle.fbs(pb, pr.left, pr.right)
+    tw, th = 8, 8
+    rg = oracle.guided_ranges(pb, d0, np.ones_like(d0, np.uint8), tw, th, 0, 1)
+    assert (rg[..., 1] - rg[..., 0] < pb.n_disp - 1).any()   # some ranges are narrower
+    d1, s1 = oracle.fbs_ranged(pb, pr.left, pr.right, tw, th, rg)
+    np.testing.assert_array_equal(d1, d0)
+    np.testing.assert_array_equal(s1, s0)
+
+
+def test_ranged_excluding_the_minimum_is_argmin_of_the_slice():
+    """A range that leaves out the true match: numpy's first-occurrence argmin
+    over the aggregated volume's slice; Eq. 10 falls back at the range ends."""
+    wl = scenes.workload("tiny")
+    pr = scenes.make_pair(wl)
+    pb = Problem.from_workload(wl)
+    _, _, agg = oracle.fbs(pb, pr.left, pr.right, want_agg=True)
+    tw, th = wl.width, wl.height                          # one tile
+    lo, hi = 9, 13
+    rg = np.array([[[lo, hi]]], np.int32)
+    d1, s1 = oracle.fbs_ranged(pb, pr.left, pr.right, tw, th, rg)
+    k = np.argmin(agg[lo - pb.d_min:hi - pb.d_min + 1], axis=0)
+    np.testing.assert_array_equal(d1, lo + k)
+    ends = (k == 0) | (k == hi - lo)
+    np.testing.assert_array_equal(s1[ends], d1[ends].astype(np.float64))
