@@ -109,6 +109,9 @@ def parse():
     ap.add_argument("--no-lr", action="store_true",
                     help="skip the left-right path (both views and Eq. 9)")
     ap.add_argument("--lr-steps", type=int, default=20)
+    ap.add_argument("--no-guided", action="store_true",
+                    help="skip the guided-search-range leg")
+    ap.add_argument("--guided-frames", type=int, default=32)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed loop, copy this many MiB device to device once "
                          "(a kernel of known traffic that calibrates rocprofv3 byte counters)")
@@ -501,6 +504,76 @@ def left_right(args, dev, wl, pair):
                         "Eq. 9 and Eq. 10 (two volumes' work)"}
 
 
+def guided(args, dev):
+    """Search ranges suggested by reliable pixels (the paper's future work)
+    against the plain full-range run, on held-out 640x480 pairs (D=96, r=10):
+    seeds from a cheap radius-3 left-right run, per-tile ranges (halo 10,
+    margin 3), the full-radius run over the ranges only."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+    from paper_1807_02044_amd import _lib as L
+    from paper_1807_02044_amd import surrogate as SG
+    import paper_1807_02044_amd as fbs
+
+    seeds = [SG.EVAL_SEED0 + 100 + i for i in range(args.guided_frames)]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(workers) as ex:
+        imgs = list(ex.map(SG._gen, seeds))
+    cw, fw = SG.workloads(seeds[0])
+    pc, pf = fbs.params_for(cw), fbs.params_for(fw)
+    W, H = fw.width, fw.height
+    Ls = [torch.from_numpy(a).to(dev) for a, _ in imgs]
+    Rs = [torch.from_numpy(b).to(dev) for _, b in imgs]
+    n = len(seeds)
+    stream = torch.cuda.Stream(device=dev)
+    tw, th = L.fbs_range_tile(pf)
+    plain = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(n)]
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    dl = torch.empty((H, W), dtype=torch.int32, device=dev)
+    valid = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    ws = torch.empty(L.fbs_lr_workspace_bytes(pc), dtype=torch.uint8, device=dev)
+    rg = torch.empty(((H + th - 1) // th, (W + tw - 1) // tw, 2), dtype=torch.int32, device=dev)
+    halo, margin = fw.radius, 3
+
+    def run_plain(i):
+        L.fbs_run(pf, Ls[i], Rs[i], None, plain[i], None, None, stream)
+
+    def run_guided(i):
+        L.fbs_run_lr(pc, Ls[i], Rs[i], 0, dl, None, valid, None, ws, stream)
+        L.fbs_guided_ranges(pf, dl, valid, halo, margin, rg, stream)
+        L.fbs_run_ranged(pf, Ls[i], Rs[i], rg, None, out, stream)
+
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            for i in range(n):
+                fn(i)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for i in range(n):
+                fn(i)
+            stream.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    t_plain = timed(run_plain)
+    t_guided = timed(run_guided)
+    bad, width = [], []
+    with torch.cuda.stream(stream):
+        for i in range(n):
+            run_guided(i)
+            bad.append(float(((out - plain[i]).abs() > 1.0).float().mean().item()))
+            width.append(float((rg[..., 1] - rg[..., 0] + 1).float().mean().item()))
+    b = np.asarray(bad)
+    return {"frames": n, "workload": f"{W}x{H} gray, d {fw.d_min}..{fw.d_max}, r={fw.radius}; "
+                                     f"seeds from r={cw.radius} left-right run",
+            "halo": halo, "margin": margin, "tile": [tw, th],
+            "plain_frames_per_s": 1.0 / t_plain, "guided_frames_per_s": 1.0 / t_guided,
+            "speedup_vs_plain": t_plain / t_guided,
+            "bad1_vs_plain_mean": float(b.mean()), "bad1_vs_plain_max": float(b.max()),
+            "mean_range_width": float(np.mean(width))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -621,6 +694,8 @@ def main():
         out["end_to_end"] = end_to_end(args, dev, wl, pair, p, stream)
     if not args.no_lr:
         out["left_right"] = left_right(args, dev, wl, pair)
+    if not args.no_guided:
+        out["guided"] = guided(args, dev)
     if not args.no_batched:
         out["batched"] = batched(args, dev)
     if not args.no_surrogate:

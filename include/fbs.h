@@ -169,9 +169,38 @@ fbs_status fbs_lrc(const fbs_params* p, const int32_t* disp_left, const int32_t*
  * part, and a window without any valid value gives -1.  From `p` only the
  * image geometry, d_min, d_max (d_max may exceed width here), radius and
  * sigma_s, sigma_r are read.  disp_in, disp_out: int32 [H][W], not
- * overlapping.  Weights and sums in float32. */
+ * overlapping.  Weights and sums in double precision. */
 fbs_status fbs_wmf(const fbs_params* p, const uint8_t* reference, const int32_t* disp_in,
                    int32_t* disp_out, void* stream);
+
+/* ---- Search ranges suggested by reliable pixels (Section V) ----
+ *
+ * The paper's future work: reliable feature points suggest the search range
+ * of their neighbourhood, and only that range is searched.  Ranges are given
+ * per tile of the matrix-core kernel (fbs_range_tile), as int32 pairs
+ * (lo, hi) of absolute disparities, [tiles_y][tiles_x][2] with
+ * tiles_x = ceil(W / tile_w), tiles_y = ceil(H / tile_h).  TAD, radius 1..10
+ * (the matrix-core kernel) only; FBS_E_UNSUPPORTED otherwise. */
+
+/* Tile shape of the ranges for `p` (host only). */
+fbs_status fbs_range_tile(const fbs_params* p, int32_t* tile_w, int32_t* tile_h);
+
+/* Ranges from seeds: a tile's range is [min - margin, max + margin] of the
+ * disparities disp_seed holds where valid != 0 (and inside [d_min, d_max])
+ * in the tile grown by `halo` pixels on each side (0..64), clipped to
+ * [d_min, d_max]; the whole range where the grown tile has no seed.  Seeds
+ * are typically the pixels a cheap run's left-right check keeps
+ * (fbs_run_lr at a small radius: disp_left and valid). */
+fbs_status fbs_guided_ranges(const fbs_params* p, const int32_t* disp_seed, const uint8_t* valid,
+                             int32_t halo, int32_t margin, int32_t* ranges, void* stream);
+
+/* fbs_run restricted to the ranges: each pixel's costs are aggregated, and
+ * its WTA and Eq. 10 run, only over its tile's range (Eq. 10 returns d* at
+ * the range's ends).  A range is clipped to [d_min, d_max]; an empty one
+ * (lo > hi after clipping) means the whole range.  disp, disp_sub as for
+ * fbs_run (either may be NULL). */
+fbs_status fbs_run_ranged(const fbs_params* p, const uint8_t* left, const uint8_t* right,
+                          const int32_t* ranges, int32_t* disp, float* disp_sub, void* stream);
 
 /* Bytes of device workspace fbs_run_lr needs for `p` (mirrored image copies,
  * the right map, the left map, and NCC's block sums).  Host only. */

@@ -11,7 +11,7 @@ from __future__ import annotations
 from typing import Optional, Tuple
 
 __all__ = ["params_for", "run", "cost", "aggregate", "wta_subpixel", "workspace", "run_lr",
-           "cost_lr", "lrc", "wmf"]
+           "cost_lr", "lrc", "wmf", "guided_ranges", "run_ranged"]
 
 
 def params_for(wl, cost_type: int = 0, ncc_radius: int = 1, flags: int = 0):
@@ -117,3 +117,24 @@ def wmf(p, reference, disp_in, stream=None):
     out = torch.empty_like(disp_in)
     _lib.fbs_wmf(p, reference, disp_in, out, stream)
     return out
+
+
+def guided_ranges(p, disp_seed, valid, halo: int, margin: int, stream=None):
+    """fbs_guided_ranges -> int32 [tiles_y][tiles_x][2] ranges."""
+    import torch
+    from . import _lib
+    tw, th = _lib.fbs_range_tile(p)
+    out = torch.empty(((p.height + th - 1) // th, (p.width + tw - 1) // tw, 2),
+                      dtype=torch.int32, device=disp_seed.device)
+    _lib.fbs_guided_ranges(p, disp_seed, valid, halo, margin, out, stream)
+    return out
+
+
+def run_ranged(p, left, right, ranges, stream=None):
+    """fbs_run_ranged -> (disp int32, disp_sub float32)."""
+    import torch
+    from . import _lib
+    disp = torch.empty((p.height, p.width), dtype=torch.int32, device=left.device)
+    sub = torch.empty((p.height, p.width), dtype=torch.float32, device=left.device)
+    _lib.fbs_run_ranged(p, left, right, ranges, disp, sub, stream)
+    return disp, sub

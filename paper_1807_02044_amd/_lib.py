@@ -38,7 +38,8 @@ FBS_PLAN_PER_TILE = 0x2
 EXPORTS = (
     "fbs_validate", "fbs_workspace_bytes", "fbs_cost", "fbs_aggregate", "fbs_wta_subpixel",
     "fbs_run", "fbs_run_variant", "fbs_cost_lr", "fbs_lrc", "fbs_lr_workspace_bytes",
-    "fbs_run_lr", "fbs_wmf", "fbs_plan_create", "fbs_plan_launch", "fbs_plan_pair_config",
+    "fbs_run_lr", "fbs_wmf", "fbs_range_tile", "fbs_guided_ranges",
+    "fbs_run_ranged", "fbs_plan_create", "fbs_plan_launch", "fbs_plan_pair_config",
     "fbs_plan_num_launches", "fbs_plan_destroy", "fbs_surrogate_num_params",
     "fbs_surrogate_create", "fbs_surrogate_destroy", "fbs_surrogate_set_params",
     "fbs_surrogate_get_params", "fbs_surrogate_features", "fbs_surrogate_cheap_run",
@@ -106,6 +107,12 @@ def lib() -> ctypes.CDLL:
         h.fbs_run_lr.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
         h.fbs_wmf.argtypes = [P, vp, vp, vp, vp]
         h.fbs_wmf.restype = ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int32)
+        h.fbs_range_tile.argtypes = [P, ip, ip]
+        h.fbs_guided_ranges.argtypes = [P, vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
+        h.fbs_run_ranged.argtypes = [P, vp, vp, vp, vp, vp, vp]
+        for f in (h.fbs_range_tile, h.fbs_guided_ranges, h.fbs_run_ranged):
+            f.restype = ctypes.c_int
         for f in (h.fbs_validate, h.fbs_workspace_bytes, h.fbs_cost, h.fbs_aggregate,
                   h.fbs_wta_subpixel, h.fbs_run, h.fbs_run_variant, h.fbs_cost_lr, h.fbs_lrc,
                   h.fbs_lr_workspace_bytes, h.fbs_run_lr):
@@ -241,6 +248,22 @@ def fbs_run_lr(p, left, right, max_diff, disp_left, disp_right, valid, disp_sub,
 def fbs_wmf(p, reference, disp_in, disp_out, stream=None):
     _check(lib().fbs_wmf(ctypes.byref(p), _ptr(reference), _ptr(disp_in), _ptr(disp_out),
                          _stream(stream)))
+
+
+def fbs_range_tile(p):
+    tw, th = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().fbs_range_tile(ctypes.byref(p), ctypes.byref(tw), ctypes.byref(th)))
+    return int(tw.value), int(th.value)
+
+
+def fbs_guided_ranges(p, disp_seed, valid, halo, margin, ranges, stream=None):
+    _check(lib().fbs_guided_ranges(ctypes.byref(p), _ptr(disp_seed), _ptr(valid), int(halo),
+                                   int(margin), _ptr(ranges), _stream(stream)))
+
+
+def fbs_run_ranged(p, left, right, ranges, disp, disp_sub, stream=None):
+    _check(lib().fbs_run_ranged(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(ranges),
+                                _ptr(disp), _ptr(disp_sub), _stream(stream)))
 
 
 def fbs_run_variant(p: FbsParams) -> int:

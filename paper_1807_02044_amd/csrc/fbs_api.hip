@@ -100,6 +100,16 @@ fbs::Tables make_tables(const fbs_params* p)
     return t;
 }
 
+fbs::Tables64 make_tables64(const fbs_params* p)
+{
+    fbs::Tables64 t;
+    const double gd = (double)p->sigma_s, gr = (double)p->sigma_r;
+    for (int k = 0; k <= FBS_MAX_RADIUS; ++k) t.gs[k] = exp(-(double)(k * k) / (gd * gd));
+    const double scale = (p->channels == 3) ? 3.0 : 1.0;
+    for (int i = 0; i < 256; ++i) t.gr[i] = exp(-(double)(i * i) / (scale * gr * gr));
+    return t;
+}
+
 size_t ncc_ws_bytes(const fbs_params* p)
 {
     const size_t b = (size_t)16 * p->width * p->height;
@@ -424,9 +434,55 @@ fbs_status fbs_wmf(const fbs_params* p, const uint8_t* reference, const int32_t*
         (const char*)disp_out < (const char*)disp_in + map)
         return fail(FBS_E_INVALID, "disp_in and disp_out overlap");
     (void)hipGetLastError();
-    return hip_status(fbs::launch_wmf(make_geom(p), make_tables(p), reference, disp_in, disp_out,
+    return hip_status(fbs::launch_wmf(make_geom(p), make_tables64(p), reference, disp_in, disp_out,
                                       (hipStream_t)stream),
                       "fbs_wmf");
+}
+
+fbs_status fbs_range_tile(const fbs_params* p, int32_t* tile_w, int32_t* tile_h)
+{
+    fbs_status st = check_params(p);
+    if (st != FBS_OK) return st;
+    const fbs::Geom g = make_geom(p);
+    if (p->cost_type != FBS_COST_TAD || (p->flags & FBS_F_FORCE_VALU) || !fbs::mfma_supported(g))
+        return fail(FBS_E_UNSUPPORTED, "search ranges need the matrix-core TAD kernel");
+    if (tile_w) *tile_w = 2 * fbs::mfma_default_cfg(g).nw;
+    if (tile_h) *tile_h = fbs::mfma_tile_rows();
+    return FBS_OK;
+}
+
+fbs_status fbs_guided_ranges(const fbs_params* p, const int32_t* disp_seed, const uint8_t* valid,
+                             int32_t halo, int32_t margin, int32_t* ranges, void* stream)
+{
+    int32_t tw = 0, th = 0;
+    fbs_status st = fbs_range_tile(p, &tw, &th);
+    if (st != FBS_OK) return st;
+    if (!disp_seed || !valid || !ranges)
+        return fail(FBS_E_INVALID, "disp_seed, valid and ranges are required");
+    if (halo < 0 || margin < 0) return fail(FBS_E_INVALID, "halo and margin must be >= 0");
+    if (halo > 64) return fail(FBS_E_UNSUPPORTED, "halo above 64");
+    if (!aligned4(disp_seed) || ((uintptr_t)ranges & 7u))
+        return fail(FBS_E_INVALID, "disp_seed must be 4-byte and ranges 8-byte aligned");
+    (void)hipGetLastError();
+    return hip_status(fbs::launch_guided_ranges(make_geom(p), disp_seed, valid, tw, th, halo, margin,
+                                                (int2*)ranges, (hipStream_t)stream),
+                      "fbs_guided_ranges");
+}
+
+fbs_status fbs_run_ranged(const fbs_params* p, const uint8_t* left, const uint8_t* right,
+                          const int32_t* ranges, int32_t* disp, float* disp_sub, void* stream)
+{
+    fbs_status st = fbs_range_tile(p, nullptr, nullptr);
+    if (st != FBS_OK) return st;
+    if (!left || !right || !ranges) return fail(FBS_E_INVALID, "left, right and ranges are required");
+    if ((uintptr_t)ranges & 7u) return fail(FBS_E_INVALID, "ranges must be 8-byte aligned");
+    if (!aligned4(disp) || !aligned4(disp_sub))
+        return fail(FBS_E_INVALID, "outputs must be 4-byte aligned");
+    if (!disp && !disp_sub) return FBS_OK;
+    (void)hipGetLastError();
+    return hip_status(fbs::launch_mfma_ranged(make_geom(p), make_tables(p), left, right,
+                                              (const int2*)ranges, disp, disp_sub, (hipStream_t)stream),
+                      "fbs_run_ranged");
 }
 
 const char* fbs_status_str(int status)

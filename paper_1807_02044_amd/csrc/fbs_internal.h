@@ -34,6 +34,12 @@ struct Tables {
     float gr[256];
 };
 
+// The same factors in double precision (the weighted median filter).
+struct Tables64 {
+    double gs[FBS_MAX_RADIUS + 1];
+    double gr[256];
+};
+
 enum CostSrc { SRC_VOLUME = 0, SRC_TAD = 1, SRC_NCC = 2 };
 
 // ---- launchers (each returns the launch status; no synchronisation) ----
@@ -54,9 +60,18 @@ hipError_t launch_lrc(const Geom& g, const int32_t* dl, const int32_t* dr, bool 
 hipError_t launch_wta_subpixel(const Geom& g, const float* agg, int32_t* disp, float* sub,
                                hipStream_t s);
 
+// Per-tile search ranges (int2 lo, hi per tile) from seed disparities.
+hipError_t launch_guided_ranges(const Geom& g, const int32_t* disp, const uint8_t* valid, int tile_w,
+                                int tile_h, int halo, int margin, int2* ranges, hipStream_t s);
+// fbs_run's matrix-core kernel with one search range per kernel tile
+// (ranges [tiles_y][tiles_x], tiles of 8 rows x 2 * mfma_default_cfg(g).nw).
+int mfma_tile_rows();  // rows of a matrix-core kernel tile
+hipError_t launch_mfma_ranged(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
+                              const int2* ranges, int32_t* disp, float* sub, hipStream_t s);
+
 // Weighted median filter of an int32 map (g.r = window radius; values
 // outside [g.dmin, g.dmin + g.D - 1] are holes).
-hipError_t launch_wmf(const Geom& g, const Tables& t, const uint8_t* img, const int32_t* din,
+hipError_t launch_wmf(const Geom& g, const Tables64& t, const uint8_t* img, const int32_t* din,
                       int32_t* dout, hipStream_t s);
 int wmf_lds_bytes(int r, int ch);
 

@@ -74,4 +74,18 @@ hipError_t launch_mfma(const Geom& g, const Tables& t, const uint8_t* L, const u
     return launch_mfma_cfg(g, t, mfma_default_cfg(g), L, R, disp, sub, agg, s);
 }
 
+int mfma_tile_rows() { return kTileH; }
+
+hipError_t launch_mfma_ranged(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
+                              const int2* ranges, int32_t* disp, float* sub, hipStream_t s)
+{
+    float scap;
+    if (!mfma_supported(g) || !scaled_cap(g, &scap)) return hipErrorInvalidValue;
+    const MfmaCfg cfg = mfma_default_cfg(g);
+    TileJob job{g, scap, cfg.nb, L, R, disp, sub, nullptr, nullptr};
+    job.ranges = ranges;
+    job.ranges_tx = (g.W + 2 * cfg.nw - 1) / (2 * cfg.nw);
+    return dispatch<FrameLauncher>(g.r, g.C, cfg.nw, job, t, s);
+}
+
 }  // namespace fbs

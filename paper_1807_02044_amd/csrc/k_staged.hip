@@ -1,13 +1,15 @@
 // k_staged.hip - the materialising kernels of the staged path:
 //   cost volume (TAD, or the paper's NCC with pre-computed block sums) and
-//   WTA + subpixel over an aggregated volume; and the small per-pixel
-//   kernels of the left-right path: image mirroring and the consistency
-//   check of Eq. 9.
+//   WTA + subpixel over an aggregated volume; the small per-pixel kernels
+//   of the left-right path (image mirroring, the consistency check of
+//   Eq. 9); and the per-tile search ranges from reliable seeds.
 //
 // The cost kernels optionally also write the right volume by dual storage
 // (Section II-A).  All of them are bound by HBM traffic: each writes or reads
 // 4*W*H*D bytes of float volume once, with lanes along x so every access is a
 // coalesced row segment of the [D][H][W] layout.
+#include <climits>
+
 #include "fbs_device.h"
 #include "fbs_internal.h"
 
@@ -202,6 +204,53 @@ __global__ __launch_bounds__(kRowThreads) void k_lrc(Geom g, const int32_t* __re
     if (right_out) right_out[row + x] = dr[row + (MIRRORED ? g.W - 1 - x : x)];
 }
 
+// Per-tile search ranges from reliable seeds (Section V, future work): tile
+// (tx, ty) of tile_w x tile_h pixels gets [min - margin, max + margin] of the
+// seed disparities (valid != 0, inside [d_min, d_max]) in the tile grown by
+// `halo` pixels, clipped to [d_min, d_max]; the whole range without seeds.
+// One workgroup per tile; lanes stride over the grown tile, then a wave and a
+// workgroup min/max reduction.
+__global__ __launch_bounds__(kRowThreads) void k_guided_ranges(Geom g, const int32_t* __restrict__ disp,
+                                                               const uint8_t* __restrict__ valid,
+                                                               int tile_w, int tile_h, int halo,
+                                                               int margin, int2* __restrict__ ranges)
+{
+    __shared__ int s_lo[kRowThreads / 64], s_hi[kRowThreads / 64];
+    const int tx = blockIdx.x, ty = blockIdx.y;
+    const int dmax = g.dmin + g.D - 1;
+    const int gw = tile_w + 2 * halo, gh = tile_h + 2 * halo;
+    const int x0 = tx * tile_w - halo, y0 = ty * tile_h - halo;
+    int lo = INT_MAX, hi = INT_MIN;
+    for (int i = threadIdx.x; i < gw * gh; i += kRowThreads) {
+        const int y = y0 + i / gw, x = x0 + i % gw;
+        if (x < 0 || x >= g.W || y < 0 || y >= g.H) continue;
+        const size_t o = (size_t)y * g.W + x;
+        const int d = disp[o];
+        if (!valid[o] || d < g.dmin || d > dmax) continue;
+        lo = min(lo, d);
+        hi = max(hi, d);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off));
+        hi = max(hi, __shfl_xor(hi, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[threadIdx.x >> 6] = lo;
+        s_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kRowThreads / 64; ++w) {
+            lo = min(lo, s_lo[w]);
+            hi = max(hi, s_hi[w]);
+        }
+        int2 r = make_int2(g.dmin, dmax);
+        if (lo <= hi) r = make_int2(max(lo - margin, g.dmin), min(hi + margin, dmax));
+        ranges[(size_t)ty * gridDim.x + tx] = r;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_cost_tad(const Geom& g, const uint8_t* L, const uint8_t* R, float* cost,
@@ -260,6 +309,15 @@ hipError_t launch_lrc(const Geom& g, const int32_t* dl, const int32_t* dr, bool 
     else
         hipLaunchKernelGGL(k_lrc<false>, grid, dim3(kRowThreads), 0, s, g, dl, dr, max_diff, valid,
                            sub, right_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_guided_ranges(const Geom& g, const int32_t* disp, const uint8_t* valid, int tile_w,
+                                int tile_h, int halo, int margin, int2* ranges, hipStream_t s)
+{
+    dim3 grid((g.W + tile_w - 1) / tile_w, (g.H + tile_h - 1) / tile_h);
+    hipLaunchKernelGGL(k_guided_ranges, grid, dim3(kRowThreads), 0, s, g, disp, valid, tile_w, tile_h,
+                       halo, margin, ranges);
     return hipGetLastError();
 }
 

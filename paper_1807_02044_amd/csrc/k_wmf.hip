@@ -1,6 +1,9 @@
 // k_wmf.hip - weighted median filter of an integer disparity map (the
 // refinement step Section II-D names beside the left-right check), with the
-// support weights of Eqs. 7-8 from the reference image.
+// support weights of Eqs. 7-8 from the reference image, in double precision
+// (weights and sums: a window whose valid values all sit far from the centre
+// in intensity keeps weights far below float's range, and only relative
+// weights within a window decide its median).
 //
 // Output per pixel: the smallest window value m whose cumulative weight (the
 // weights of window values <= m) reaches half the window's total; values
@@ -13,7 +16,8 @@
 // lane-major so the 64 lanes of a wave hit 64 distinct banks), walks the
 // cumulative sum to the bin that crosses half the total, and narrows the
 // range to that bin; ceil(log16 D) levels reach single values (2 for D <= 256).
-// Each level recomputes the window's weights (no per-tap storage).
+// Each level recomputes the window's weights (no per-tap storage).  The
+// weight tables come from the host in double precision.
 #include "fbs_internal.h"
 
 namespace fbs {
@@ -33,24 +37,24 @@ __host__ __device__ inline WmfLayout wmf_layout(int r, int ch)
 {
     WmfLayout l;
     l.side = kWmfTile + 2 * r;
-    l.off_hist = (256 + 32) * 4;                              // range LUT, spatial factors
-    l.off_disp = l.off_hist + kBins * kWmfThreads * 4;
+    l.off_hist = (256 + 32) * 8;                              // range LUT, spatial factors
+    l.off_disp = l.off_hist + kBins * kWmfThreads * 8;
     l.off_img = l.off_disp + l.side * l.side * 4;
     l.bytes = l.off_img + ((l.side * l.side * ch + 15) & ~15);
     return l;
 }
 
 template <int CH>
-__global__ __launch_bounds__(kWmfThreads) void k_wmf(Geom g, Tables tb, const uint8_t* __restrict__ img,
+__global__ __launch_bounds__(kWmfThreads) void k_wmf(Geom g, Tables64 tb, const uint8_t* __restrict__ img,
                                                      const int32_t* __restrict__ din,
                                                      int32_t* __restrict__ dout)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int r = g.r;
     const WmfLayout lay = wmf_layout(r, CH);
-    float* s_gr = reinterpret_cast<float*>(smem);
-    float* s_gs = s_gr + 256;
-    float* s_hist = reinterpret_cast<float*>(smem + lay.off_hist);
+    double* s_gr = reinterpret_cast<double*>(smem);
+    double* s_gs = s_gr + 256;
+    double* s_hist = reinterpret_cast<double*>(smem + lay.off_hist);
     int32_t* s_d = reinterpret_cast<int32_t*>(smem + lay.off_disp);
     uint8_t* s_img = smem + lay.off_img;
     const int tid = threadIdx.x;
@@ -59,7 +63,7 @@ __global__ __launch_bounds__(kWmfThreads) void k_wmf(Geom g, Tables tb, const ui
     const int dmax = g.dmin + g.D - 1;
 
     for (int i = tid; i < 256; i += kWmfThreads) s_gr[i] = tb.gr[i];
-    if (tid < 32) s_gs[tid] = tid <= FBS_MAX_RADIUS ? tb.gs[tid] : 0.0f;
+    if (tid < 32) s_gs[tid] = tid <= FBS_MAX_RADIUS ? tb.gs[tid] : 0.0;
     // halo positions off the image are holes; their image bytes are never read
     for (int i = tid; i < side * side; i += kWmfThreads) {
         const int ty = i / side, tx = i - ty * side;
@@ -85,21 +89,21 @@ __global__ __launch_bounds__(kWmfThreads) void k_wmf(Geom g, Tables tb, const ui
     for (int c = 0; c < CH; ++c) ip[c] = s_img[cpos * CH + c];
 
     int lo = g.dmin, span = g.D;
-    float below = 0.0f, total = 0.0f, half = 0.0f;
+    double below = 0.0, total = 0.0, half = 0.0;
     bool first = true;
     int32_t out = -1;
     for (;;) {
         const int bw = (span + kBins - 1) / kBins;
 #pragma unroll
-        for (int b = 0; b < kBins; ++b) s_hist[b * kWmfThreads + tid] = 0.0f;
+        for (int b = 0; b < kBins; ++b) s_hist[b * kWmfThreads + tid] = 0.0;
         for (int dy = -r; dy <= r; ++dy) {
-            const float wy = s_gs[dy < 0 ? -dy : dy];
+            const double wy = s_gs[dy < 0 ? -dy : dy];
             const int row = (ly + r + dy) * side + lx + r;
             for (int dx = -r; dx <= r; ++dx) {
                 const int q = row + dx;
                 const int v = s_d[q];
                 if (v < 0) continue;
-                float w = wy * s_gs[dx < 0 ? -dx : dx];
+                double w = wy * s_gs[dx < 0 ? -dx : dx];
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     const int di = (int)s_img[q * CH + c] - ip[c];
@@ -111,17 +115,17 @@ __global__ __launch_bounds__(kWmfThreads) void k_wmf(Geom g, Tables tb, const ui
             }
         }
         if (first) {
-            if (!(total > 0.0f)) break;  // no valid value in the window
-            half = 0.5f * total;
+            if (!(total > 0.0)) break;  // no valid value (or all weights below double's range)
+            half = 0.5 * total;
             first = false;
         }
         // the first bin whose cumulative weight reaches half; if rounding
         // leaves every bin short, the last bin that holds weight
         int pick = -1, last = -1;
-        float cum = below, before_last = below;
+        double cum = below, before_last = below;
         for (int b = 0; b < kBins && pick < 0; ++b) {
-            const float h = s_hist[b * kWmfThreads + tid];
-            if (h > 0.0f) {
+            const double h = s_hist[b * kWmfThreads + tid];
+            if (h > 0.0) {
                 last = b;
                 before_last = cum;
             }
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(kWmfThreads) void k_wmf(Geom g, Tables tb, const ui
 
 int wmf_lds_bytes(int r, int ch) { return wmf_layout(r, ch).bytes; }
 
-hipError_t launch_wmf(const Geom& g, const Tables& t, const uint8_t* img, const int32_t* din,
+hipError_t launch_wmf(const Geom& g, const Tables64& t, const uint8_t* img, const int32_t* din,
                       int32_t* dout, hipStream_t s)
 {
     dim3 grid((g.W + kWmfTile - 1) / kWmfTile, (g.H + kWmfTile - 1) / kWmfTile);

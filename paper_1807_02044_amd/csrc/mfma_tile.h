@@ -178,6 +178,11 @@ struct TileJob {
     float* sub;
     float* agg;
     uint16_t* feat;  // FEAT tiles only: learned-surrogate features [H][W][32] BF16
+    // Optional per-tile search ranges (lo, hi) [tiles_y][ranges_tx]: each tile
+    // searches only its range (clipped to the job's; an empty range means the
+    // whole one).  Only for disp / sub outputs (not agg or feat).
+    const int2* ranges;
+    int ranges_tx;
 };
 
 // The caller has put the range LUT by signed difference (kLutN floats, entry
@@ -318,13 +323,24 @@ __device__ __forceinline__ void recheck_pixel(const TileJob& job, const uint8_t*
 // at the end - so the results do not depend on the path, the slab depth or
 // the waves per workgroup.
 template <int R, int CH, int NW, bool FEAT = false, bool CO = false>
-__device__ __forceinline__ void mfma_tile(const TileJob& job, int tile_x, int tile_y,
+__device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int tile_y,
                                           unsigned char* smem, int tid)
 {
+#pragma clang fp contract(off)
+    TileJob job = job_in;
+    if (job.ranges) {
+        // this tile's search range: every step below sees it as the job's range
+        const int2 rg = job.ranges[tile_y * job.ranges_tx + tile_x];
+        const int lo = __builtin_amdgcn_readfirstlane(max(rg.x, job.g.dmin));
+        const int hi = __builtin_amdgcn_readfirstlane(min(rg.y, job.g.dmin + job.g.D - 1));
+        if (lo <= hi) {
+            job.g.dmin = lo;
+            job.g.D = hi - lo + 1;
+        }
+    }
     // Every floating-point operation here rounds as written: a fused
     // multiply-add in place of w - hi (w a product) would change lo, and the
     // compiler's choice could differ between kernels that share this code.
-#pragma clang fp contract(off)
     constexpr int kThreads = 64 * NW, kTileW = 2 * NW;
     const Geom& g = job.g;
     const int nb = job.nb;

@@ -106,8 +106,12 @@ def test_wmf_fills_the_checked_map():
     pb = Problem(wl.d_min, wl.d_max, 3, 3.0, 10.0)
     n_tie = _check(pb, pr.left, din_h, got)
     assert n_tie <= got.size // 1000
+    # a removed match is refilled exactly where its window holds a valid value
+    from scipy import ndimage
+    has_valid = ndimage.maximum_filter((din_h >= 0).astype(np.uint8), size=7, mode="constant") > 0
+    np.testing.assert_array_equal(got >= 0, has_valid)
     holes = din_h < 0
-    assert (got[holes] >= 0).mean() > 0.9   # nearly every removed match is refilled
+    print(f"holes {int(holes.sum())}, refilled {int((got[holes] >= 0).sum())}", flush=True)
 
 
 def test_wmf_rejects_overlap_and_bad_radius():
