@@ -219,6 +219,25 @@ fbs_status fbs_run_lr(const fbs_params* p, const uint8_t* left, const uint8_t* r
                       int32_t max_diff, int32_t* disp_left, int32_t* disp_right, uint8_t* valid,
                       float* disp_sub, void* workspace, void* stream);
 
+/* Bytes of the static device scratch of fbs_run_lr_noalloc (per GPU). */
+#define FBS_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* fbs_run_lr without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * outputs and arithmetic as fbs_run_lr; the workspace is a static device
+ * array of FBS_NOALLOC_SCRATCH_BYTES on each GPU, which the library holds
+ * until the process ends (its address is looked up on the first call on
+ * each device, on the current device).  FBS_E_UNSUPPORTED when
+ * fbs_lr_workspace_bytes(p) exceeds FBS_NOALLOC_SCRATCH_BYTES (e.g. above
+ * about 5.5 Mpixel gray or 3.3 Mpixel RGB).  Every call on one GPU uses the
+ * same scratch: calls that overlap on one GPU (different streams, threads
+ * or processes' graphs replaying concurrently) race and must be ordered by
+ * the caller.  Nothing in the scratch needs to start at zero. */
+fbs_status fbs_run_lr_noalloc(const fbs_params* p, const uint8_t* left, const uint8_t* right,
+                              int32_t max_diff, int32_t* disp_left, int32_t* disp_right,
+                              uint8_t* valid, float* disp_sub, void* stream);
+
 /* ---- Batched plans: many pairs of uneven sizes in one graph launch ---- */
 
 typedef struct fbs_plan fbs_plan;

@@ -31,6 +31,8 @@ FBS_MAX_DISP = 1024
 
 FBS_F_FORCE_VALU = 0x1
 
+FBS_NOALLOC_SCRATCH_BYTES = 32 << 20
+
 FBS_PLAN_TUNE = 0x1
 FBS_PLAN_PER_TILE = 0x2
 
@@ -38,7 +40,7 @@ FBS_PLAN_PER_TILE = 0x2
 EXPORTS = (
     "fbs_validate", "fbs_workspace_bytes", "fbs_cost", "fbs_aggregate", "fbs_wta_subpixel",
     "fbs_run", "fbs_run_variant", "fbs_cost_lr", "fbs_lrc", "fbs_lr_workspace_bytes",
-    "fbs_run_lr", "fbs_wmf", "fbs_range_tile", "fbs_guided_ranges",
+    "fbs_run_lr", "fbs_run_lr_noalloc", "fbs_wmf", "fbs_range_tile", "fbs_guided_ranges",
     "fbs_run_ranged", "fbs_plan_create", "fbs_plan_launch", "fbs_plan_pair_config",
     "fbs_plan_num_launches", "fbs_plan_destroy", "fbs_surrogate_num_params",
     "fbs_surrogate_create", "fbs_surrogate_destroy", "fbs_surrogate_set_params",
@@ -113,6 +115,8 @@ def lib() -> ctypes.CDLL:
         h.fbs_run_ranged.argtypes = [P, vp, vp, vp, vp, vp, vp]
         for f in (h.fbs_range_tile, h.fbs_guided_ranges, h.fbs_run_ranged):
             f.restype = ctypes.c_int
+        h.fbs_run_lr_noalloc.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
+        h.fbs_run_lr_noalloc.restype = ctypes.c_int
         for f in (h.fbs_validate, h.fbs_workspace_bytes, h.fbs_cost, h.fbs_aggregate,
                   h.fbs_wta_subpixel, h.fbs_run, h.fbs_run_variant, h.fbs_cost_lr, h.fbs_lrc,
                   h.fbs_lr_workspace_bytes, h.fbs_run_lr):
@@ -264,6 +268,13 @@ def fbs_guided_ranges(p, disp_seed, valid, halo, margin, ranges, stream=None):
 def fbs_run_ranged(p, left, right, ranges, disp, disp_sub, stream=None):
     _check(lib().fbs_run_ranged(ctypes.byref(p), _ptr(left), _ptr(right), _ptr(ranges),
                                 _ptr(disp), _ptr(disp_sub), _stream(stream)))
+
+
+def fbs_run_lr_noalloc(p, left, right, max_diff, disp_left, disp_right, valid, disp_sub,
+                       stream=None):
+    _check(lib().fbs_run_lr_noalloc(ctypes.byref(p), _ptr(left), _ptr(right), int(max_diff),
+                                    _ptr(disp_left), _ptr(disp_right), _ptr(valid),
+                                    _ptr(disp_sub), _stream(stream)))
 
 
 def fbs_run_variant(p: FbsParams) -> int:
