@@ -20,8 +20,9 @@
 // only formed when the aggregated volume is requested.
 //
 // Workgroup: 8 waves, one 16-pixel group per wave, covering an 8x16 pixel
-// tile.  The left tile and the right strip it can match are staged in LDS as
-// bytes once.  The disparity axis is walked in slabs of nb 16-disparity
+// tile.  The left tile and the right strip it can match are staged in LDS once
+// (gray: a byte per pixel; RGB: a dword per pixel, so every pixel access is
+// aligned).  The disparity axis is walked in slabs of nb 16-disparity
 // blocks: per slab all waves build the fp16 cost planes of the tile's window
 // union in LDS (each cost computed once per workgroup), then every wave runs
 // its MFMA chains.  Lane group g (lanes 16g..16g+15) of the 16x16 result holds
@@ -91,19 +92,23 @@ __host__ __device__ constexpr Cfg cfg_of(int r, int tile_w)
 __host__ __device__ constexpr int align16(int b) { return (b + 15) & ~15; }
 
 struct MfmaLayout {
-    int lwb, rwb;     // bytes per left-tile / right-strip row (channels interleaved)
+    int lwb, rwb;     // bytes per left-tile / right-strip row (pixel_bytes(ch) per pixel)
     int off_wx, off_wy, off_L, off_R, off_cost;
     int bytes;
 };
+
+// Bytes per pixel in the LDS image rows: gray 1; RGB 4 (R, G, B, 0), so that a
+// pixel is one aligned dword for the byte-wise SAD and the range weights.
+__host__ __device__ constexpr int pixel_bytes(int ch) { return ch == 3 ? 4 : 1; }
 
 __host__ __device__ constexpr MfmaLayout mfma_layout(int r, int ch, int D, int nb, int nw)
 {
     const int tile_w = 2 * nw;
     const Cfg c = cfg_of(r, tile_w);
     MfmaLayout m{};
-    m.lwb = ch * c.LW;
+    m.lwb = pixel_bytes(ch) * c.LW;
     // +16: slack for the unaligned reads of the last octet of a row
-    m.rwb = (ch * (c.LW + D - 1) + 16 + 3) & ~3;
+    m.rwb = (pixel_bytes(ch) * (c.LW + D - 1) + 16 + 3) & ~3;
     m.off_wx = (kLutN + 32) * 4;  // after the signed range LUT and the spatial factors
     m.off_wy = m.off_wx + tile_w * c.LW * 4;
     m.off_L = m.off_wy + align16(kTileH * c.LH * 4);
@@ -150,14 +155,6 @@ __device__ __forceinline__ void load_unaligned(const uint8_t* base, int off, uin
     for (int i = 0; i <= N; ++i) t[i] = a[i];
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] = __builtin_amdgcn_alignbyte(t[i + 1], t[i], sh);
-}
-
-// Pixel j (bytes 3j..3j+2, zero-extended) of 8 interleaved RGB pixels.
-__device__ __forceinline__ uint32_t rgb_pixel(const uint32_t (&a)[6], int j)
-{
-    const int b = 3 * j, i = b >> 2, s = b & 3;
-    const uint32_t hi = a[i + 1 < 6 ? i + 1 : 5];
-    return __builtin_amdgcn_perm(hi, a[i], 0x0c000000u | ((s + 2) << 16) | ((s + 1) << 8) | s);
 }
 
 // fp16 pair (s0, s1) of two integers below 1024
@@ -210,7 +207,7 @@ __device__ __forceinline__ uint32_t bf16_bits(float f)
 // costs at disparity indices base + l + 64 j (j < 4).  Every lane returns the
 // pixel's disparity index and subpixel disparity.  Used only where the
 // fp16-split weights cannot order near ties.
-template <int R, int CH>
+template <int R, int CH, int PB = pixel_bytes(CH)>
 __device__ __forceinline__ void recheck_pass(const Geom& g, const uint8_t* s_L, const uint8_t* s_R,
                                              int LWB, int RWB, int prow, int pcol, int x, int y,
                                              int base, int lane, double (&a)[4])
@@ -221,7 +218,7 @@ __device__ __forceinline__ void recheck_pass(const Geom& g, const uint8_t* s_L, 
     const double tau = (double)g.tau;
     int lp[CH];
 #pragma unroll
-    for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(prow + R) * LWB + (pcol + R) * CH + ch];
+    for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(prow + R) * LWB + (pcol + R) * PB + ch];
     double num[4] = {0.0, 0.0, 0.0, 0.0};
     double den = 0.0;
 #pragma unroll 1
@@ -237,7 +234,7 @@ __device__ __forceinline__ void recheck_pass(const Geom& g, const uint8_t* s_L, 
             double d2 = 0.0;
 #pragma unroll
             for (int ch = 0; ch < CH; ++ch) {
-                lq[ch] = s_L[row * LWB + col * CH + ch];
+                lq[ch] = s_L[row * LWB + col * PB + ch];
                 const double t = (double)(lq[ch] - lp[ch]);
                 d2 += t * t;
             }
@@ -254,7 +251,7 @@ __device__ __forceinline__ void recheck_pass(const Geom& g, const uint8_t* s_L, 
                         int sad = 0;
 #pragma unroll
                         for (int ch = 0; ch < CH; ++ch)
-                            sad += abs(lq[ch] - (int)s_R[row * RWB + (col + dmax - d) * CH + ch]);
+                            sad += abs(lq[ch] - (int)s_R[row * RWB + (col + dmax - d) * PB + ch]);
                         const double m = (double)sad / (double)CH;
                         c = m < tau ? m : tau;
                     }
@@ -353,7 +350,8 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     constexpr Cfg C = cfg_of(R, kTileW);
     constexpr int GH = C.GH, GW = C.GW, OPR = C.OPR, NOCT = C.NOCT, NCH = C.NCH;
     constexpr int LH = C.LH, LW = C.LW, PS = C.PS;
-    constexpr int LWB = CH * LW;
+    constexpr int PB = pixel_bytes(CH);  // bytes per pixel in LDS
+    constexpr int LWB = PB * LW;
     static_assert(C.GX * C.GY == NW, "one group per wave");
 
     const int D = g.D;
@@ -391,29 +389,35 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
         s_wy[i] = (dy <= R && y >= 0 && y < g.H) ? s_gs[dy] * kWScale : 0.0f;
     }
     {
-        // Bytes off the image are never weighted (their window positions have
+        // Pixels off the image are never weighted (their window positions have
         // zero weight, and right pixels left of the image are replaced by the
         // cap), so they only need to be finite: read them from clamped
         // in-bounds addresses instead of branching.  4 bytes per thread and
-        // iteration, all loads issued before the LDS writes.
-        const int rowbytes = g.W * CH;
-        auto stage = [&](uint8_t* dst, int wb, int xb0, const uint8_t* src) {
+        // iteration (gray: 4 pixels; RGB: one pixel and a zero byte), all loads
+        // issued before the LDS writes.
+        auto stage = [&](uint8_t* dst, int wb, int x0, const uint8_t* src) {
             const int n4 = LH * wb / 4;
 #pragma unroll 2
             for (int i = tid; i < n4; i += kThreads) {
                 const int row = (4 * i) / wb, cb = 4 * i - row * wb;
                 const size_t rbase = (size_t)min(max(oy + row, 0), g.H - 1) * g.stride;
                 uint32_t v = 0;
+                if constexpr (CH == 1) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int xb = min(max(xb0 + cb + e, 0), rowbytes - 1);
-                    v |= (uint32_t)src[rbase + xb] << (8 * e);
+                    for (int e = 0; e < 4; ++e) {
+                        const int xb = min(max(x0 + cb + e, 0), g.W - 1);
+                        v |= (uint32_t)src[rbase + xb] << (8 * e);
+                    }
+                } else {
+                    const size_t xb = (size_t)min(max(x0 + cb / 4, 0), g.W - 1) * 3;
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) v |= (uint32_t)src[rbase + xb + e] << (8 * e);
                 }
                 reinterpret_cast<uint32_t*>(dst)[i] = v;
             }
         };
-        stage(s_L, LWB, ox * CH, Lg);
-        stage(s_R, RWB, rox * CH, Rg);
+        stage(s_L, LWB, ox, Lg);
+        stage(s_R, RWB, rox, Rg);
     }
     __syncthreads();
 
@@ -428,7 +432,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     // w = wx(dx) * wy(dy) * prod_ch gr(|dI_ch|) * 2^14, then w = hi + lo
     uint32_t lp[CH];
 #pragma unroll
-    for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(prow + R) * LWB + (pcol + R) * CH + ch];
+    for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(prow + R) * LWB + (pcol + R) * PB + ch];
     auto chunk_weights = [&](int c, h8& whc, h8& wlc) {
 #pragma clang fp contract(off)
         const int o = min(4 * c + gq, NOCT - 1);  // octets past the union: weight 0
@@ -439,18 +443,18 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
         const float4 wx0 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U);
         const float4 wx1 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U + 4);
         const float wx[8] = {wx0.x, wx0.y, wx0.z, wx0.w, wx1.x, wx1.y, wx1.z, wx1.w};
-        // 8 pixels x CH channels of the left image, as dwords (U*CH is a multiple of 4)
-        uint32_t lq[2 * CH];
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(s_L + V * LWB + U * CH);
+        // 8 pixels of the left image, as dwords (U is a multiple of 8)
+        uint32_t lq[2 * PB];
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(s_L + V * LWB + U * PB);
 #pragma unroll
-        for (int i = 0; i < 2 * CH; ++i) lq[i] = q[i];
+        for (int i = 0; i < 2 * PB; ++i) lq[i] = q[i];
         float wa[8], wb[8];  // w = wa * wb
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             float wr = 1.0f;
 #pragma unroll
             for (int ch = 0; ch < CH; ++ch) {
-                const int b = CH * j + ch;
+                const int b = PB * j + ch;
                 const int iv = (int)((lq[b >> 2] >> (8 * (b & 3))) & 0xffu);
                 const float f = s_gr[iv - (int)lp[ch]];
                 wr = ch == 0 ? f : wr * f;
@@ -601,20 +605,20 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                     *reinterpret_cast<h8*>(dst + jm * PS) = out;
                 }
             } else {
-                const uint2* lq = reinterpret_cast<const uint2*>(s_L + row * LWB + 24 * oc);
-                const uint2 a0 = lq[0], a1 = lq[1], a2 = lq[2];
-                const uint32_t la[6] = {a0.x, a0.y, a1.x, a1.y, a2.x, a2.y};
-                uint32_t lpx[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) lpx[j] = rgb_pixel(la, j);
+                const uint4* lq = reinterpret_cast<const uint4*>(s_L + row * LWB + 32 * oc);
+                const uint4 a0 = lq[0], a1 = lq[1];
+                const uint32_t lpx[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
                 for (int jm = 0; jm < 4; ++jm) {
                     const int d = g.dmin + min(k0 + jm, D - 1);
-                    uint32_t ra[6];
-                    load_unaligned<6>(s_R, row * RWB + 24 * oc + 3 * (dmax - d), ra);
+                    // 8 aligned pixel dwords of the right strip
+                    const uint32_t* rq = reinterpret_cast<const uint32_t*>(s_R + row * RWB + 32 * oc + 4 * (dmax - d));
+                    uint32_t ra[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) ra[j] = rq[j];
                     uint32_t sad[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) sad[j] = __builtin_amdgcn_sad_u8(lpx[j], rgb_pixel(ra, j), 0u);
+                    for (int j = 0; j < 8; ++j) sad[j] = __builtin_amdgcn_sad_u8(lpx[j], ra[j], 0u);
                     h8 out;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
