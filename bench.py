@@ -35,10 +35,11 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0     # dense fp16 matrix peak
 # (FETCH_SIZE, WRITE_SIZE), each scaled by what the counter reads for a
 # 256 MiB device copy.  Valid only for the kernel source they were taken on.
 MEASURED_TRAFFIC = {
-    "slanted8_450x375_gray_d0-63_r7": {
+    "rich25_1400x1000_rgb_d0-159_r10": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "d6a5a65a1b05d2502c174ccbcd5795ac28c9c4e05fd69577eada823e4ffba9c1",
-        "bytes_per_launch": 4.669e6,
+        "sha256": "378e554936c921542f9f2f8cc3a976a04f843d451a608b7aa09bae14ff6c5356",
+        # FETCH_SIZE 27117.7 KiB x 2.0 + WRITE_SIZE 10937.5 KiB x 1.0
+        "bytes_per_launch": 66.74e6,
     },
 }
 
@@ -46,7 +47,26 @@ MEASURED_TRAFFIC = {
 # Counter-derived utilisation of the fused kernel (rocprofv3 PMC runs of the
 # profiled command): VALU issue and matrix-pipe busy shares of the SIMD time
 # of one launch.  Valid only for the kernel source they were taken on.
-MEASURED_UTIL = {}
+MEASURED_UTIL = {
+    "rich25_1400x1000_rgb_d0-159_r10": {
+        "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
+        "sha256": "378e554936c921542f9f2f8cc3a976a04f843d451a608b7aa09bae14ff6c5356",
+        # SQ_INSTS_VALU x 4 cycles and SQ_VALU_MFMA_BUSY_CYCLES over the SIMD-cycles
+        # of a 1.623 ms launch (1024 SIMDs at 2.4 GHz); SQ_LDS_BANK_CONFLICT over
+        # SQ_LDS_IDX_ACTIVE
+        "valu_issue_frac": 0.522,
+        "mfma_busy_frac": 0.127,
+        "lds_bank_conflict_frac": 0.416,
+        "counters_kernel_avg_ms": 1.623,
+    },
+    "slanted8_450x375_gray_d0-63_r7": {
+        "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
+        "sha256": "378e554936c921542f9f2f8cc3a976a04f843d451a608b7aa09bae14ff6c5356",
+        "valu_issue_frac": 0.567,
+        "mfma_busy_frac": 0.121,
+        "counters_kernel_avg_ms": 0.05516,
+    },
+}
 
 
 def _sources_sha(sources):
@@ -69,18 +89,10 @@ def measured_utilisation(workload: str):
 
 
 def measured_traffic(workload: str):
-    import hashlib
     m = MEASURED_TRAFFIC.get(workload)
-    if not m:
+    if not m or _sources_sha(m["sources"]) != m["sha256"]:
         return None
-    h = hashlib.sha256()
-    try:
-        for src in m["sources"]:
-            with open(os.path.join(ROOT, src), "rb") as f:
-                h.update(f.read())
-    except OSError:
-        return None
-    return m["bytes_per_launch"] if h.hexdigest() == m["sha256"] else None
+    return m["bytes_per_launch"]
 
 
 def parse():
@@ -409,15 +421,17 @@ def time_fused(L, p, Ld, Rd, disp, sub, ws, stream, steps, warmup):
     return wall, kern_ms
 
 
-def extra_config(name, args, dev, force_valu):
-    """One smaller single-pair workload: frames/s and the kernel time."""
+def extra_config(name, args, dev, force_valu, cost_type=0):
+    """One smaller single-pair workload: frames/s and the kernel time
+    (cost_type 1: the paper's NCC cost, Eqs. 1-3, on the vector-ALU kernel)."""
     import torch
     from paper_1807_02044_amd import _lib as L
     from paper_1807_02044_amd import scenes
     import paper_1807_02044_amd as fbs
     wl = scenes.workload(name)
     pair = scenes.make_pair(wl)
-    p = fbs.params_for(wl, flags=L.FBS_F_FORCE_VALU if force_valu else 0)
+    p = fbs.params_for(wl, cost_type=cost_type,
+                       flags=L.FBS_F_FORCE_VALU if force_valu else 0)
     Ld = torch.from_numpy(pair.left).to(dev)
     Rd = torch.from_numpy(pair.right).to(dev)
     disp = torch.empty((wl.height, wl.width), dtype=torch.int32, device=dev)
@@ -426,10 +440,16 @@ def extra_config(name, args, dev, force_valu):
     steps = max(20, min(200, args.steps * 10))
     wall, kern_ms = time_fused(L, p, Ld, Rd, disp, sub, fbs.workspace(p, dev), stream, steps, 10)
     avg = sum(kern_ms) / len(kern_ms)
-    return {"workload": wl.name, "frames_per_s": steps / wall,
+    mfma = L.fbs_run_variant(p) == 1
+    tflops = 2.0 * wl.work_taps / (avg * 1e-3) / 1e12
+    peak = PEAK_FP16_MFMA_TFLOPS if mfma else PEAK_FP32_VALU_TFLOPS
+    util = measured_utilisation(wl.name) if mfma else None
+    return {"workload": wl.name, "cost": "ncc" if cost_type == 1 else "tad", **(util or {}),
+            "frames_per_s": steps / wall,
             "gpix_disp_tap_per_s": wl.work_taps * steps / wall / 1e9,
-            "kernel_avg_ms": avg, "kernel": "k_fbs_mfma" if L.fbs_run_variant(p) else "k_valu",
-            "achieved_tflops": 2.0 * wl.work_taps / (avg * 1e-3) / 1e12, "steps": steps}
+            "kernel_avg_ms": avg, "kernel": "k_fbs_mfma" if mfma else "k_valu",
+            "achieved_tflops": tflops, "peak_tflops": peak, "frac": tflops / peak,
+            "steps": steps}
 
 
 def end_to_end(args, dev, wl, pair, p, stream):
@@ -688,8 +708,9 @@ def main():
         out["two_streams"] = two_streams
     if not args.no_extra_configs:
         out["other_configs"] = [extra_config(n, args, dev, args.force_valu)
-                                for n in ("tiny", "mid") if n != wl.name.split("_")[0]
-                                and n != args.workload]
+                                for n in ("tiny", "mid") if n != args.workload]
+        # the paper's own cost (NCC, block radius 1) on the 450x375 pair
+        out["other_configs"].append(extra_config("mid", args, dev, False, cost_type=1))
     if not args.no_e2e:
         out["end_to_end"] = end_to_end(args, dev, wl, pair, p, stream)
     if not args.no_lr:

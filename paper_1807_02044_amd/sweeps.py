@@ -13,9 +13,10 @@ It is computed over three regions of the left view, as in the paper:
                    of a ground-truth disparity jump larger than 2.
 
 Estimates come from the library's full path with the left-right check
-(fbs_run_lr: Eq. 9 then Eq. 10); a pixel whose match the check removed has no
-estimate and counts as an error.  The sweep varies gamma_d, gamma_r and rho
-one at a time around a base point and times the fused path per rho.
+(fbs_run_lr: Eq. 9 then Eq. 10; a pixel whose match the check removed has no
+estimate and counts as an error), and from the left-view path alone (fbs_run,
+every pixel estimated).  The sweep varies gamma_d, gamma_r and rho one at a
+time around a base point and times the fused path per rho.
 
 Run:  python -m paper_1807_02044_amd.sweeps [--out FILE]
 """
@@ -106,10 +107,11 @@ def run_point(wl, pair, dev, radius: int, gamma_d: float, gamma_r: float,
     Ld = torch.from_numpy(pair.left).to(dev)
     Rd = torch.from_numpy(pair.right).to(dev)
     dl, dr, valid, sub = fbs.run_lr(p, Ld, Rd, max_diff)
+    _, sub_left = fbs.run(p, Ld, Rd)
     torch.cuda.synchronize()
-    est = sub.cpu().numpy()
     out = {"rho": radius, "gamma_d": gamma_d, "gamma_r": gamma_r,
-           "e_pep": evaluate(est, pair),
+           "e_pep": evaluate(sub.cpu().numpy(), pair),
+           "e_pep_left": evaluate(sub_left.cpu().numpy(), pair),
            "lrc_kept": float(valid.float().mean().item())}
     if timed_steps > 0:
         disp = torch.empty((wl.height, wl.width), dtype=torch.int32, device=dev)
@@ -145,6 +147,7 @@ def sweep(wl=None, seeds: Iterable[int] = (2, 12, 22), rhos=(1, 2, 3, 4, 5, 6, 7
         keys = points[0]["e_pep"].keys()
         res = dict(points[0])
         res["e_pep"] = {k: float(np.mean([p["e_pep"][k] for p in points])) for k in keys}
+        res["e_pep_left"] = {k: float(np.mean([p["e_pep_left"][k] for p in points])) for k in keys}
         res["lrc_kept"] = float(np.mean([p["lrc_kept"] for p in points]))
         return res
 
@@ -176,14 +179,16 @@ def table(res: dict) -> str:
              f"base {res['base']}"]
     for name in ("gamma_d", "gamma_r", "rho"):
         lines.append("")
-        hdr = f"{name:>8} {'non_occ':>9} {'textl':>9} {'discont':>9} {'kept':>6}"
+        hdr = (f"{name:>8} {'non_occ':>9} {'textl':>9} {'discont':>9} {'kept':>6} "
+               f"{'left:non_occ':>13} {'textl':>9} {'discont':>9}")
         if name == "rho":
             hdr += f" {'fbs_run_ms':>11}"
         lines.append(hdr)
         for r in res[name]:
-            e = r["e_pep"]
+            e, f = r["e_pep"], r["e_pep_left"]
             row = (f"{r[name]:>8} {e['non_occ']:9.2f} {e['non_occ_textl']:9.2f} "
-                   f"{e['non_occ_discont']:9.2f} {r['lrc_kept']:6.3f}")
+                   f"{e['non_occ_discont']:9.2f} {r['lrc_kept']:6.3f} {f['non_occ']:13.2f} "
+                   f"{f['non_occ_textl']:9.2f} {f['non_occ_discont']:9.2f}")
             if name == "rho" and "fbs_run_ms" in r:
                 row += f" {r['fbs_run_ms']:11.4f}"
             lines.append(row)

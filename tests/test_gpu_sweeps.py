@@ -29,6 +29,11 @@ def test_point_matches_oracle_measurement(rho, gd, gr):
         n = int(sweeps.regions(pr)[k].sum())
         assert abs(res["e_pep"][k] - v) <= 100.0 * 2 / n, (k, res["e_pep"][k], v)
     assert res["lrc_kept"] == pytest.approx(float(valid.mean()), abs=4.0 / valid.size)
+    _, sub_left = oracle.fbs(pb, pr.left, pr.right)
+    want_left = sweeps.evaluate(sub_left, pr)
+    for k, v in want_left.items():
+        n = int(sweeps.regions(pr)[k].sum())
+        assert abs(res["e_pep_left"][k] - v) <= 100.0 * 2 / n, (k, res["e_pep_left"][k], v)
 
 
 def test_runtime_grows_with_rho():
