@@ -143,27 +143,6 @@ __device__ __forceinline__ h2 bytes23_f16(uint32_t v)
     return __builtin_bit_cast(h2, __builtin_amdgcn_perm(0x64646464u, v, 0x04030402u));
 }
 
-// Dwords w[0..N-1] of an LDS byte array starting at an arbitrary byte offset:
-// N+1 aligned dword reads (the row slack of the strip keeps the last in bounds).
-template <int N>
-__device__ __forceinline__ void load_unaligned(const uint8_t* base, int off, uint32_t (&w)[N])
-{
-    const uint32_t* a = reinterpret_cast<const uint32_t*>(base) + (off >> 2);
-    const uint32_t sh = (uint32_t)(off & 3);
-    uint32_t t[N + 1];
-#pragma unroll
-    for (int i = 0; i <= N; ++i) t[i] = a[i];
-#pragma unroll
-    for (int i = 0; i < N; ++i) w[i] = __builtin_amdgcn_alignbyte(t[i + 1], t[i], sh);
-}
-
-// fp16 pair (s0, s1) of two integers below 1024
-__device__ __forceinline__ h2 small_int_pair(uint32_t s0, uint32_t s1)
-{
-    const h2 off = {(_Float16)1024.0f, (_Float16)1024.0f};
-    return __builtin_bit_cast(h2, (s0 | (s1 << 16)) | 0x64006400u) - off;
-}
-
 // One tile's worth of work, shared by the per-frame and the batched kernels.
 struct TileJob {
     Geom g;
@@ -567,71 +546,101 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     const h2 cap2 = {hcap, hcap};
 
     // Cost planes of blocks b0 .. b0+nbb-1: plane p = 16*bb + 4*gm + jm holds
-    // disparity index k = gm*Q + 4*(b0+bb) + jm.  An item is one octet (8
-    // positions of a tile row) at the 4 consecutive disparities jm = 0..3 of
-    // one (bb, gm).  Costs of positions off the image or of padded disparities
-    // are never weighted, so any finite value will do there.
+    // disparity index k = gm*Q + 4*(b0+bb) + jm.  A thread owns one octet (8
+    // positions of a tile row), reads its left pixels once, and walks the
+    // quads (bb, gm) kQStride apart; per quad it forms the 8 positions at the
+    // 4 consecutive disparities d0 .. d0+3 (jm = 0..3), whose right pixels
+    // x - d are the 11 strip columns c = 8*oc + dmax - d0 - 3 + i, i = j - jm + 3.
+    // Costs of positions off the image or of padded disparities (k >= D) are
+    // never weighted, so any finite value will do there: padded disparities
+    // read up to 15 pixels before their strip row, which stays inside the LDS
+    // tile (the left tile precedes the strip).
+    constexpr int kPairs = LH * kOct;
+    static_assert(kPairs <= kThreads, "one octet per thread");
+    constexpr int kQStride = kThreads / kPairs;
+    const int b_q0 = tid / kPairs, b_pair = tid - b_q0 * kPairs;
+    const int b_row = b_pair / kOct, b_oc = b_pair - b_row * kOct;
     auto build_slab = [&](int b0, int nbb) {
-        const int items = 4 * nbb * LH * kOct;
+        if (b_q0 >= kQStride) return;
+        const int x0 = ox + 8 * b_oc;
+        _Float16* dst0 = s_cost + b_row * LW + 8 * b_oc;
+        // a cost that pairs with a right pixel left of the image is the cap
+        auto left_fill = [&](h8& out, int d) {
+            const int thr = d - x0;  // positions j < thr: x - d < 0
+            if (thr > 0) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (j < thr) out[j] = hcap;
+            }
+        };
+        if constexpr (CH == 1) {
+            const uint2 lv = *reinterpret_cast<const uint2*>(s_L + b_row * LWB + 8 * b_oc);
+            const h2 l[4] = {bytes01_f16(lv.x), bytes23_f16(lv.x), bytes01_f16(lv.y), bytes23_f16(lv.y)};
 #pragma unroll 1
-        for (int it = tid; it < items; it += kThreads) {
-            const int oc = it % kOct;
-            const int t = it / kOct;
-            const int row = t % LH;
-            const int quad = t / LH;                      // 4*bb + gm
-            const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
-            const int x0 = ox + 8 * oc;
-            _Float16* dst = s_cost + (size_t)(4 * quad) * PS + row * LW + 8 * oc;
-            if (CH == 1) {
-                const uint2 lv = *reinterpret_cast<const uint2*>(s_L + row * LWB + 8 * oc);
-                const h2 l0 = bytes01_f16(lv.x), l1 = bytes23_f16(lv.x);
-                const h2 l2 = bytes01_f16(lv.y), l3 = bytes23_f16(lv.y);
+            for (int quad = b_q0; quad < 4 * nbb; quad += kQStride) {
+                const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
+                const int d0 = g.dmin + k0;
+                // bytes c0 .. c11 of strip columns from 8*oc + dmax - d0 - 3 on
+                const int cb = b_row * RWB + 8 * b_oc + (dmax - d0 - 3);
+                const int ab = cb & ~3;
+                const uint32_t sh = (uint32_t)(cb - ab);
+                const uint32_t* wq = reinterpret_cast<const uint32_t*>(s_R + ab);
+                const uint32_t w0 = wq[0], w1 = wq[1], w2 = wq[2], w3 = wq[3];
+                const uint32_t u0 = __builtin_amdgcn_alignbyte(w1, w0, sh);
+                const uint32_t u1 = __builtin_amdgcn_alignbyte(w2, w1, sh);
+                const uint32_t u2 = __builtin_amdgcn_alignbyte(w3, w2, sh);
+                const uint32_t v0 = __builtin_amdgcn_alignbyte(u1, u0, 1u);
+                const uint32_t v1 = __builtin_amdgcn_alignbyte(u2, u1, 1u);
+                const uint32_t v2 = u2 >> 8;
+                // E[k] = (c[2k], c[2k+1]), O[k] = (c[2k+1], c[2k+2]) as 1024 + byte
+                const h2 E[5] = {bytes01_f16(u0), bytes23_f16(u0), bytes01_f16(u1), bytes23_f16(u1), bytes01_f16(u2)};
+                const h2 O[5] = {bytes01_f16(v0), bytes23_f16(v0), bytes01_f16(v1), bytes23_f16(v1), bytes01_f16(v2)};
+                _Float16* dst = dst0 + (size_t)(4 * quad) * PS;
 #pragma unroll
                 for (int jm = 0; jm < 4; ++jm) {
-                    const int d = g.dmin + min(k0 + jm, D - 1);
-                    uint32_t r[2];
-                    load_unaligned<2>(s_R, row * RWB + 8 * oc + (dmax - d), r);
-                    const h2 c0 = __builtin_elementwise_min(__builtin_elementwise_abs(l0 - bytes01_f16(r[0])), cap2);
-                    const h2 c1 = __builtin_elementwise_min(__builtin_elementwise_abs(l1 - bytes23_f16(r[0])), cap2);
-                    const h2 c2 = __builtin_elementwise_min(__builtin_elementwise_abs(l2 - bytes01_f16(r[1])), cap2);
-                    const h2 c3 = __builtin_elementwise_min(__builtin_elementwise_abs(l3 - bytes23_f16(r[1])), cap2);
-                    h8 out = {c0[0], c0[1], c1[0], c1[1], c2[0], c2[1], c3[0], c3[1]};
-                    const int thr = d - x0;                       // positions j < thr: x - d < 0
-                    if (thr > 0) {
-#pragma unroll
-                        for (int j = 0; j < 8; ++j)
-                            if (j < thr) out[j] = hcap;
-                    }
-                    *reinterpret_cast<h8*>(dst + jm * PS) = out;
-                }
-            } else {
-                const uint4* lq = reinterpret_cast<const uint4*>(s_L + row * LWB + 32 * oc);
-                const uint4 a0 = lq[0], a1 = lq[1];
-                const uint32_t lpx[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-#pragma unroll
-                for (int jm = 0; jm < 4; ++jm) {
-                    const int d = g.dmin + min(k0 + jm, D - 1);
-                    // 8 aligned pixel dwords of the right strip
-                    const uint32_t* rq = reinterpret_cast<const uint32_t*>(s_R + row * RWB + 32 * oc + 4 * (dmax - d));
-                    uint32_t ra[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) ra[j] = rq[j];
-                    uint32_t sad[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) sad[j] = __builtin_amdgcn_sad_u8(lpx[j], ra[j], 0u);
+                    // positions (2i, 2i+1) pair with c[2i - jm + 3], c[2i - jm + 4]
                     h8 out;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const h2 c = __builtin_elementwise_min(small_int_pair(sad[2 * i], sad[2 * i + 1]), cap2);
+                        const h2 r = jm == 0 ? O[i + 1] : jm == 1 ? E[i + 1] : jm == 2 ? O[i] : E[i];
+                        const h2 c = __builtin_elementwise_min(__builtin_elementwise_abs(l[i] - r), cap2);
                         out[2 * i] = c[0];
                         out[2 * i + 1] = c[1];
                     }
-                    const int thr = d - x0;
-                    if (thr > 0) {
+                    left_fill(out, d0 + jm);
+                    *reinterpret_cast<h8*>(dst + jm * PS) = out;
+                }
+            }
+        } else {
+            const uint4* lq = reinterpret_cast<const uint4*>(s_L + b_row * LWB + 32 * b_oc);
+            const uint4 a0 = lq[0], a1 = lq[1];
+            const uint32_t lpx[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            const h2 off = {(_Float16)1024.0f, (_Float16)1024.0f};
+#pragma unroll 1
+            for (int quad = b_q0; quad < 4 * nbb; quad += kQStride) {
+                const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
+                const int d0 = g.dmin + k0;
+                // the 11 aligned pixel dwords of strip columns 8*oc + dmax - d0 - 3 on
+                const uint32_t* rq = reinterpret_cast<const uint32_t*>(s_R + b_row * RWB + 32 * b_oc) + (dmax - d0 - 3);
+                uint32_t rr[11];
 #pragma unroll
-                        for (int j = 0; j < 8; ++j)
-                            if (j < thr) out[j] = hcap;
+                for (int i = 0; i < 11; ++i) rr[i] = rq[i];
+                _Float16* dst = dst0 + (size_t)(4 * quad) * PS;
+#pragma unroll
+                for (int jm = 0; jm < 4; ++jm) {
+                    h8 out;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        // the two channel sums land on the fp16 exponent of 1024
+                        // (sums <= 765), low and high half: the pair (1024 + s0, 1024 + s1)
+                        const int j0 = 2 * i, j1 = j0 + 1;
+                        uint32_t v = __builtin_amdgcn_sad_u8(lpx[j0], rr[j0 - jm + 3], 0x64006400u);
+                        v = __builtin_amdgcn_sad_hi_u8(lpx[j1], rr[j1 - jm + 3], v);
+                        const h2 c = __builtin_elementwise_min(__builtin_bit_cast(h2, v) - off, cap2);
+                        out[2 * i] = c[0];
+                        out[2 * i + 1] = c[1];
                     }
+                    left_fill(out, d0 + jm);
                     *reinterpret_cast<h8*>(dst + jm * PS) = out;
                 }
             }
