@@ -93,9 +93,13 @@ __host__ __device__ constexpr int align16(int b) { return (b + 15) & ~15; }
 
 struct MfmaLayout {
     int lwb, rwb;     // bytes per left-tile / right-strip row (pixel_bytes(ch) per pixel)
-    int off_wx, off_wy, off_L, off_R, off_cost;
+    int off_wx, off_wy, off_L, off_R, off_L4, off_cost;
     int bytes;
 };
+
+// Left tile again as 16-bit words 4 * I per channel (RGB: R, G, B, 0): the
+// byte offsets of the range factors, so that a factor's address is one add.
+__host__ __device__ constexpr int pixel_words(int ch) { return ch == 3 ? 4 : 1; }
 
 // Bytes per pixel in the LDS image rows: gray 1; RGB 4 (R, G, B, 0), so that a
 // pixel is one aligned dword for the byte-wise SAD and the range weights.
@@ -113,7 +117,8 @@ __host__ __device__ constexpr MfmaLayout mfma_layout(int r, int ch, int D, int n
     m.off_wy = m.off_wx + tile_w * c.LW * 4;
     m.off_L = m.off_wy + align16(kTileH * c.LH * 4);
     m.off_R = m.off_L + align16(c.LH * m.lwb);
-    m.off_cost = m.off_R + align16(c.LH * m.rwb);
+    m.off_L4 = m.off_R + align16(c.LH * m.rwb);
+    m.off_cost = m.off_L4 + align16(c.LH * c.LW * pixel_words(ch) * 2);
     m.bytes = m.off_cost + 16 * nb * c.PS * 2;
     return m;
 }
@@ -344,6 +349,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     float* s_wy = reinterpret_cast<float*>(smem + lay.off_wy);
     uint8_t* s_L = smem + lay.off_L;
     uint8_t* s_R = smem + lay.off_R;
+    uint16_t* s_L4 = reinterpret_cast<uint16_t*>(smem + lay.off_L4);
     _Float16* s_cost = reinterpret_cast<_Float16*>(smem + lay.off_cost);
 
     const int lane = tid & 63, wave = tid >> 6;
@@ -373,8 +379,8 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
         // cap), so they only need to be finite: read them from clamped
         // in-bounds addresses instead of branching.  4 bytes per thread and
         // iteration (gray: 4 pixels; RGB: one pixel and a zero byte), all loads
-        // issued before the LDS writes.
-        auto stage = [&](uint8_t* dst, int wb, int x0, const uint8_t* src) {
+        // issued before the LDS writes.  The left tile also goes to s_L4.
+        auto stage = [&](uint8_t* dst, int wb, int x0, const uint8_t* src, auto words_c) {
             const int n4 = LH * wb / 4;
 #pragma unroll 2
             for (int i = tid; i < n4; i += kThreads) {
@@ -393,10 +399,16 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                     for (int e = 0; e < 3; ++e) v |= (uint32_t)src[rbase + xb + e] << (8 * e);
                 }
                 reinterpret_cast<uint32_t*>(dst)[i] = v;
+                if constexpr (decltype(words_c)::value) {
+                    // the same 4 bytes (gray: 4 pixels; RGB: R, G, B, 0) as 4 * byte in 16-bit words
+                    const uint32_t w0 = ((v & 0xffu) | ((v & 0xff00u) << 8)) << 2;
+                    const uint32_t w1 = (((v >> 16) & 0xffu) | ((v >> 8) & 0xff0000u)) << 2;
+                    reinterpret_cast<uint2*>(s_L4)[i] = make_uint2(w0, w1);
+                }
             }
         };
-        stage(s_L, LWB, ox, Lg);
-        stage(s_R, RWB, rox, Rg);
+        stage(s_L, LWB, ox, Lg, std::true_type{});
+        stage(s_R, RWB, rox, Rg, std::false_type{});
     }
     __syncthreads();
 
@@ -412,6 +424,11 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     uint32_t lp[CH];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(prow + R) * LWB + (pcol + R) * PB + ch];
+    // range factor of channel ch for a neighbour of intensity I: the float at
+    // byte offset 4 * I from gb[ch]
+    const uint8_t* gb[CH];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) gb[ch] = reinterpret_cast<const uint8_t*>(s_gr - (int)lp[ch]);
     auto chunk_weights = [&](int c, h8& whc, h8& wlc) {
 #pragma clang fp contract(off)
         const int o = min(4 * c + gq, NOCT - 1);  // octets past the union: weight 0
@@ -422,20 +439,27 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
         const float4 wx0 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U);
         const float4 wx1 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U + 4);
         const float wx[8] = {wx0.x, wx0.y, wx0.z, wx0.w, wx1.x, wx1.y, wx1.z, wx1.w};
-        // 8 pixels of the left image, as dwords (U is a multiple of 8)
-        uint32_t lq[2 * PB];
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(s_L + V * LWB + U * PB);
+        // 8 pixels of the left image as words 4 * I (U is a multiple of 8)
+        constexpr int PW = pixel_words(CH);
+        uint32_t lq[4 * PW];
+        const uint4* q = reinterpret_cast<const uint4*>(s_L4 + (V * LW + U) * PW);
 #pragma unroll
-        for (int i = 0; i < 2 * PB; ++i) lq[i] = q[i];
+        for (int i = 0; i < PW; ++i) {
+            const uint4 t = q[i];
+            lq[4 * i] = t.x;
+            lq[4 * i + 1] = t.y;
+            lq[4 * i + 2] = t.z;
+            lq[4 * i + 3] = t.w;
+        }
         float wa[8], wb[8];  // w = wa * wb
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             float wr = 1.0f;
 #pragma unroll
             for (int ch = 0; ch < CH; ++ch) {
-                const int b = PB * j + ch;
-                const int iv = (int)((lq[b >> 2] >> (8 * (b & 3))) & 0xffu);
-                const float f = s_gr[iv - (int)lp[ch]];
+                const int wi = PW * j + ch;  // word index
+                const uint32_t off = (wi & 1) ? lq[wi >> 1] >> 16 : lq[wi >> 1] & 0xffffu;
+                const float f = *reinterpret_cast<const float*>(gb[ch] + off);
                 wr = ch == 0 ? f : wr * f;
             }
             wa[j] = wx[j] * wy;
@@ -546,42 +570,42 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     const h2 cap2 = {hcap, hcap};
 
     // Cost planes of blocks b0 .. b0+nbb-1: plane p = 16*bb + 4*gm + jm holds
-    // disparity index k = gm*Q + 4*(b0+bb) + jm.  A thread owns one octet (8
-    // positions of a tile row), reads its left pixels once, and walks the
-    // quads (bb, gm) kQStride apart; per quad it forms the 8 positions at the
-    // 4 consecutive disparities d0 .. d0+3 (jm = 0..3), whose right pixels
-    // x - d are the 11 strip columns c = 8*oc + dmax - d0 - 3 + i, i = j - jm + 3.
-    // Costs of positions off the image or of padded disparities (k >= D) are
-    // never weighted, so any finite value will do there: padded disparities
-    // read up to 15 pixels before their strip row, which stays inside the LDS
-    // tile (the left tile precedes the strip).
+    // disparity index k = gm*Q + 4*(b0+bb) + jm.  An item is one octet (8
+    // positions of a tile row) of one quad (bb, gm) at the 4 consecutive
+    // disparities d0 .. d0+3 (jm = 0..3), whose right pixels x - d are the 11
+    // strip columns c = 8*oc + dmax - d0 - 3 + i, i = j - jm + 3.  Items are
+    // spread evenly over the workgroup (octet index fastest), stepped without
+    // divisions.  Costs of positions off the image or of padded disparities
+    // (k >= D) are never weighted, so any finite value will do there: padded
+    // disparities read up to 15 pixels before their strip row, which stays
+    // inside the LDS tile (the left tile precedes the strip).
     constexpr int kPairs = LH * kOct;
-    static_assert(kPairs <= kThreads, "one octet per thread");
-    constexpr int kQStride = kThreads / kPairs;
-    const int b_q0 = tid / kPairs, b_pair = tid - b_q0 * kPairs;
-    const int b_row = b_pair / kOct, b_oc = b_pair - b_row * kOct;
+    static_assert(kPairs <= kThreads, "a step covers every octet");
+    const int b_q0 = tid / kPairs, b_p0 = tid - b_q0 * kPairs;
     auto build_slab = [&](int b0, int nbb) {
-        if (b_q0 >= kQStride) return;
-        const int x0 = ox + 8 * b_oc;
-        _Float16* dst0 = s_cost + b_row * LW + 8 * b_oc;
-        // a cost that pairs with a right pixel left of the image is the cap
-        auto left_fill = [&](h8& out, int d) {
-            const int thr = d - x0;  // positions j < thr: x - d < 0
-            if (thr > 0) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    if (j < thr) out[j] = hcap;
-            }
-        };
-        if constexpr (CH == 1) {
-            const uint2 lv = *reinterpret_cast<const uint2*>(s_L + b_row * LWB + 8 * b_oc);
-            const h2 l[4] = {bytes01_f16(lv.x), bytes23_f16(lv.x), bytes01_f16(lv.y), bytes23_f16(lv.y)};
+        const h2 off = {(_Float16)1024.0f, (_Float16)1024.0f};
+        int pair = b_p0, quad = b_q0;
 #pragma unroll 1
-            for (int quad = b_q0; quad < 4 * nbb; quad += kQStride) {
-                const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
-                const int d0 = g.dmin + k0;
+        while (quad < 4 * nbb) {
+            const int row = pair / kOct, oc = pair - row * kOct;
+            const int x0 = ox + 8 * oc;
+            const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
+            const int d0 = g.dmin + k0;
+            _Float16* dst = s_cost + (size_t)(4 * quad) * PS + row * LW + 8 * oc;
+            // a cost that pairs with a right pixel left of the image is the cap
+            auto left_fill = [&](h8& out, int d) {
+                const int thr = d - x0;  // positions j < thr: x - d < 0
+                if (thr > 0) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (j < thr) out[j] = hcap;
+                }
+            };
+            if constexpr (CH == 1) {
+                const uint2 lv = *reinterpret_cast<const uint2*>(s_L + row * LWB + 8 * oc);
+                const h2 l[4] = {bytes01_f16(lv.x), bytes23_f16(lv.x), bytes01_f16(lv.y), bytes23_f16(lv.y)};
                 // bytes c0 .. c11 of strip columns from 8*oc + dmax - d0 - 3 on
-                const int cb = b_row * RWB + 8 * b_oc + (dmax - d0 - 3);
+                const int cb = row * RWB + 8 * oc + (dmax - d0 - 3);
                 const int ab = cb & ~3;
                 const uint32_t sh = (uint32_t)(cb - ab);
                 const uint32_t* wq = reinterpret_cast<const uint32_t*>(s_R + ab);
@@ -595,7 +619,6 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                 // E[k] = (c[2k], c[2k+1]), O[k] = (c[2k+1], c[2k+2]) as 1024 + byte
                 const h2 E[5] = {bytes01_f16(u0), bytes23_f16(u0), bytes01_f16(u1), bytes23_f16(u1), bytes01_f16(u2)};
                 const h2 O[5] = {bytes01_f16(v0), bytes23_f16(v0), bytes01_f16(v1), bytes23_f16(v1), bytes01_f16(v2)};
-                _Float16* dst = dst0 + (size_t)(4 * quad) * PS;
 #pragma unroll
                 for (int jm = 0; jm < 4; ++jm) {
                     // positions (2i, 2i+1) pair with c[2i - jm + 3], c[2i - jm + 4]
@@ -610,22 +633,15 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                     left_fill(out, d0 + jm);
                     *reinterpret_cast<h8*>(dst + jm * PS) = out;
                 }
-            }
-        } else {
-            const uint4* lq = reinterpret_cast<const uint4*>(s_L + b_row * LWB + 32 * b_oc);
-            const uint4 a0 = lq[0], a1 = lq[1];
-            const uint32_t lpx[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-            const h2 off = {(_Float16)1024.0f, (_Float16)1024.0f};
-#pragma unroll 1
-            for (int quad = b_q0; quad < 4 * nbb; quad += kQStride) {
-                const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
-                const int d0 = g.dmin + k0;
+            } else {
+                const uint4* lq = reinterpret_cast<const uint4*>(s_L + row * LWB + 32 * oc);
+                const uint4 a0 = lq[0], a1 = lq[1];
+                const uint32_t lpx[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
                 // the 11 aligned pixel dwords of strip columns 8*oc + dmax - d0 - 3 on
-                const uint32_t* rq = reinterpret_cast<const uint32_t*>(s_R + b_row * RWB + 32 * b_oc) + (dmax - d0 - 3);
+                const uint32_t* rq = reinterpret_cast<const uint32_t*>(s_R + row * RWB + 32 * oc) + (dmax - d0 - 3);
                 uint32_t rr[11];
 #pragma unroll
                 for (int i = 0; i < 11; ++i) rr[i] = rq[i];
-                _Float16* dst = dst0 + (size_t)(4 * quad) * PS;
 #pragma unroll
                 for (int jm = 0; jm < 4; ++jm) {
                     h8 out;
@@ -643,6 +659,13 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                     left_fill(out, d0 + jm);
                     *reinterpret_cast<h8*>(dst + jm * PS) = out;
                 }
+            }
+            // next item: kThreads further in (quad, octet) order
+            pair += kThreads % kPairs;
+            quad += kThreads / kPairs;
+            if (pair >= kPairs) {
+                pair -= kPairs;
+                ++quad;
             }
         }
     };
