@@ -129,8 +129,9 @@ fbs_status fbs_run(const fbs_params* p, const uint8_t* left, const uint8_t* righ
                    int32_t* disp, float* disp_sub, float* agg_out, void* workspace,
                    void* stream);
 
-/* Which fused kernel fbs_run picks for `p`: 1 = matrix-core (MFMA) kernel,
- * 0 = vector-ALU kernel.  Host only; FBS_E_* on invalid `p`. */
+/* Which fused kernel fbs_run picks for `p`: 1 = matrix-core (MFMA) kernel
+ * (TAD; or NCC with ncc_radius <= 1), 0 = vector-ALU kernel.  Host only;
+ * FBS_E_* on invalid `p`. */
 int fbs_run_variant(const fbs_params* p);
 
 /* ---- Both views: right volume, right map, left-right check ----

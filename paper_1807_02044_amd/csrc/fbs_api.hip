@@ -132,14 +132,17 @@ fbs_status check_map_params(const fbs_params* p)
     return FBS_OK;
 }
 
-// The fused path on validated parameters: NCC block sums then the vector-ALU
-// kernel, or TAD on the matrix cores where they apply, else the vector ALUs.
+// The fused path on validated parameters: NCC on the matrix cores where they
+// apply (gray, block radius <= 1), else block sums then the vector-ALU kernel;
+// TAD on the matrix cores where they apply, else the vector ALUs.
 fbs_status run_fused(const fbs_params* p, const fbs::Geom& g, const uint8_t* left,
                      const uint8_t* right, int32_t* disp, float* disp_sub, float* agg_out,
                      int2* stats, hipStream_t s, const char* what)
 {
     const fbs::Tables t = make_tables(p);
     if (p->cost_type == FBS_COST_NCC) {
+        if (!(p->flags & FBS_F_FORCE_VALU) && fbs::mfma_ncc_supported(g))
+            return hip_status(fbs::launch_mfma_ncc(g, t, left, right, disp, disp_sub, agg_out, s), what);
         fbs_status st = hip_status(fbs::launch_ncc_stats(g, left, right, stats, s), what);
         if (st != FBS_OK) return st;
         return hip_status(fbs::launch_valu(g, t, fbs::SRC_NCC, left, right, nullptr, stats, agg_out,
@@ -310,8 +313,10 @@ int fbs_run_variant(const fbs_params* p)
 {
     fbs_status st = check_params(p);
     if (st != FBS_OK) return st;
-    if (p->cost_type != FBS_COST_TAD || (p->flags & FBS_F_FORCE_VALU)) return 0;
-    return fbs::mfma_supported(make_geom(p)) ? 1 : 0;
+    if (p->flags & FBS_F_FORCE_VALU) return 0;
+    const fbs::Geom g = make_geom(p);
+    if (p->cost_type == FBS_COST_NCC) return fbs::mfma_ncc_supported(g) ? 1 : 0;
+    return fbs::mfma_supported(g) ? 1 : 0;
 }
 
 fbs_status fbs_run(const fbs_params* p, const uint8_t* left, const uint8_t* right, int32_t* disp,

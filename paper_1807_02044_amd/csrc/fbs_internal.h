@@ -88,6 +88,8 @@ struct MfmaCfg {
     int nb;  // 16-disparity blocks per LDS slab
 };
 bool mfma_supported(const Geom& g);
+// NCC frames on the matrix cores (gray, block radius <= 1)
+bool mfma_ncc_supported(const Geom& g);
 float mfma_scaled_cap(const Geom& g);
 int mfma_max_nb(const Geom& g, int nw);
 bool mfma_nw_valid(const Geom& g, int nw);   // 4, 8 or 12 waves and the layout fits
@@ -100,6 +102,8 @@ hipError_t launch_mfma_features(const Geom& g, const Tables& t, const uint8_t* L
 int mfma_lds_bytes(const Geom& g, int nb, int nw);
 hipError_t launch_mfma(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
                        int32_t* disp, float* sub, float* agg, hipStream_t s);
+hipError_t launch_mfma_ncc(const Geom& g, const Tables& t, const uint8_t* L, const uint8_t* R,
+                           int32_t* disp, float* sub, float* agg, hipStream_t s);
 hipError_t launch_mfma_cfg(const Geom& g, const Tables& t, const MfmaCfg& cfg, const uint8_t* L,
                            const uint8_t* R, int32_t* disp, float* sub, float* agg, hipStream_t s);
 

@@ -94,6 +94,12 @@ __host__ __device__ constexpr int align16(int b) { return (b + 15) & ~15; }
 struct MfmaLayout {
     int lwb, rwb;     // bytes per left-tile / right-strip row (pixel_bytes(ch) per pixel)
     int off_wx, off_wy, off_L, off_R, off_L4, off_cost;
+    // NCC tiles only: the left tile and the right strip with a one-pixel
+    // border (rows of nlw / nrw bytes), and per pixel the block sum (int) and
+    // 1 / sqrt(n * sum I^2 - (sum I)^2) (double, 0 where that is not positive)
+    // of the union positions (LH x LW) and of the strip columns (LH x SW)
+    int nlw, nrw, sw;
+    int off_nL, off_nR, off_sl, off_rl, off_sr, off_rr;
     int bytes;
 };
 
@@ -105,21 +111,34 @@ __host__ __device__ constexpr int pixel_words(int ch) { return ch == 3 ? 4 : 1; 
 // pixel is one aligned dword for the byte-wise SAD and the range weights.
 __host__ __device__ constexpr int pixel_bytes(int ch) { return ch == 3 ? 4 : 1; }
 
-__host__ __device__ constexpr MfmaLayout mfma_layout(int r, int ch, int D, int nb, int nw)
+__host__ __device__ constexpr MfmaLayout mfma_layout(int r, int ch, int D, int nb, int nw, bool ncc = false)
 {
     const int tile_w = 2 * nw;
     const Cfg c = cfg_of(r, tile_w);
     MfmaLayout m{};
     m.lwb = pixel_bytes(ch) * c.LW;
     // +16: slack for the unaligned reads of the last octet of a row
-    m.rwb = (pixel_bytes(ch) * (c.LW + D - 1) + 16 + 3) & ~3;
+    m.rwb = ncc ? 0 : (pixel_bytes(ch) * (c.LW + D - 1) + 16 + 3) & ~3;
     m.off_wx = (kLutN + 32) * 4;  // after the signed range LUT and the spatial factors
     m.off_wy = m.off_wx + tile_w * c.LW * 4;
     m.off_L = m.off_wy + align16(kTileH * c.LH * 4);
     m.off_R = m.off_L + align16(c.LH * m.lwb);
     m.off_L4 = m.off_R + align16(c.LH * m.rwb);
     m.off_cost = m.off_L4 + align16(c.LH * c.LW * pixel_words(ch) * 2);
-    m.bytes = m.off_cost + 16 * nb * c.PS * 2;
+    if (ncc) {
+        m.sw = c.LW + D - 1;
+        m.nlw = (c.LW + 2 + 3) & ~3;
+        m.nrw = (m.sw + 2 + 16 + 3) & ~3;
+        m.off_nL = m.off_cost;
+        m.off_nR = m.off_nL + align16((c.LH + 2) * m.nlw);
+        m.off_sl = m.off_nR + align16((c.LH + 2) * m.nrw);
+        m.off_rl = m.off_sl + align16(c.LH * c.LW * 4);
+        m.off_sr = m.off_rl + align16(c.LH * c.LW * 8);
+        m.off_rr = m.off_sr + align16(c.LH * m.sw * 4);
+        m.off_cost = m.off_rr + align16(c.LH * m.sw * 8);
+    }
+    // NCC costs are not integers: each block has hi and lo planes
+    m.bytes = m.off_cost + (ncc ? 32 : 16) * nb * c.PS * 2;
     return m;
 }
 
@@ -191,10 +210,36 @@ __device__ __forceinline__ uint32_t bf16_bits(float f)
 // costs at disparity indices base + l + 64 j (j < 4).  Every lane returns the
 // pixel's disparity index and subpixel disparity.  Used only where the
 // fp16-split weights cannot order near ties.
-template <int R, int CH, int PB = pixel_bytes(CH)>
+// NCC tiles: the bordered image tiles and the per-pixel block terms in LDS
+// (layout in MfmaLayout), the union width and the block radius.
+struct NccTile {
+    const uint8_t* nL;
+    const uint8_t* nR;
+    const int* sl;
+    const double* rl;
+    const int* sr;
+    const double* rr;
+    int nlw, nrw, sw, lw, nr;
+};
+
+// NCC cost 1 - c of Eq. 1 at union position (row, col) and disparity d (the
+// right pixel is strip column col + dmax - d), from the cross term and the
+// block terms, in double
+__device__ __forceinline__ double ncc_cost_lds(const NccTile& t, int row, int col, int sc)
+{
+    int slr = 0;
+    for (int jr = 1 - t.nr; jr <= 1 + t.nr; ++jr)
+        for (int jc = 1 - t.nr; jc <= 1 + t.nr; ++jc)
+            slr += (int)t.nL[(row + jr) * t.nlw + col + jc] * (int)t.nR[(row + jr) * t.nrw + sc + jc];
+    const int n = (2 * t.nr + 1) * (2 * t.nr + 1);
+    const int num = n * slr - t.sl[row * t.lw + col] * t.sr[row * t.sw + sc];
+    return 1.0 - (double)num * t.rl[row * t.lw + col] * t.rr[row * t.sw + sc];
+}
+
+template <int R, int CH, bool NCC = false, int PB = pixel_bytes(CH)>
 __device__ __forceinline__ void recheck_pass(const Geom& g, const uint8_t* s_L, const uint8_t* s_R,
                                              int LWB, int RWB, int prow, int pcol, int x, int y,
-                                             int base, int lane, double (&a)[4])
+                                             int base, int lane, double (&a)[4], const NccTile& nt)
 {
     const int D = g.D, dmax = g.dmin + D - 1;
     const double igd = 1.0 / ((double)g.gd * (double)g.gd);
@@ -230,8 +275,10 @@ __device__ __forceinline__ void recheck_pass(const Geom& g, const uint8_t* s_L, 
                 const int k = base + lane + 64 * j;
                 if (k >= 0 && k < D) {
                     const int d = g.dmin + k;
-                    double c = tau;
-                    if (qx - d >= 0) {
+                    double c = NCC ? 2.0 : tau;
+                    if (NCC) {
+                        if (qx - d >= 0) c = ncc_cost_lds(nt, row, col, col + dmax - d);
+                    } else if (qx - d >= 0) {
                         int sad = 0;
 #pragma unroll
                         for (int ch = 0; ch < CH; ++ch)
@@ -248,10 +295,10 @@ __device__ __forceinline__ void recheck_pass(const Geom& g, const uint8_t* s_L, 
     for (int j = 0; j < 4; ++j) a[j] = num[j] / den;
 }
 
-template <int R, int CH>
+template <int R, int CH, bool NCC>
 __device__ __forceinline__ void recheck_pixel(const TileJob& job, const uint8_t* s_L, const uint8_t* s_R,
                                               int LWB, int RWB, int prow, int pcol, int X0, int Y0,
-                                              int lane, int& k_out, float& ds_out)
+                                              int lane, int& k_out, float& ds_out, const NccTile& nt)
 {
     const Geom& g = job.g;
     const int D = g.D;
@@ -262,7 +309,7 @@ __device__ __forceinline__ void recheck_pixel(const TileJob& job, const uint8_t*
 #pragma unroll 1
     for (int base = 0; base < D; base += 256) {
         double a[4];
-        recheck_pass<R, CH>(g, s_L, s_R, LWB, RWB, prow, pcol, x, y, base, lane, a);
+        recheck_pass<R, CH, NCC>(g, s_L, s_R, LWB, RWB, prow, pcol, x, y, base, lane, a, nt);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int k = base + lane + 64 * j;
@@ -285,7 +332,7 @@ __device__ __forceinline__ void recheck_pixel(const TileJob& job, const uint8_t*
     double ds = (double)(g.dmin + bk);
     if (bk > 0 && bk < D - 1) {
         double a[4];
-        recheck_pass<R, CH>(g, s_L, s_R, LWB, RWB, prow, pcol, x, y, bk - 1, lane, a);
+        recheck_pass<R, CH, NCC>(g, s_L, s_R, LWB, RWB, prow, pcol, x, y, bk - 1, lane, a, nt);
         const double cm = __shfl(a[0], 0), cp = __shfl(a[0], 2);
         const double dnm = 2.0 * cm + 2.0 * cp - 4.0 * bv;
         if (dnm > 0.0) ds += (cm - cp) / dnm;
@@ -303,7 +350,7 @@ __device__ __forceinline__ void recheck_pixel(const TileJob& job, const uint8_t*
 // same way - hi and lo products in two chains over the chunks in order, summed
 // at the end - so the results do not depend on the path, the slab depth or
 // the waves per workgroup.
-template <int R, int CH, int NW, bool FEAT = false, bool CO = false>
+template <int R, int CH, int NW, bool FEAT = false, bool CO = false, bool NCC = false>
 __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int tile_y,
                                           unsigned char* smem, int tid)
 {
@@ -341,7 +388,8 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     const int D = g.D;
     const int nblk = (D + 15) >> 4;   // 16-disparity blocks
     const int Q = nblk * 4;           // disparities per lane group
-    const MfmaLayout lay = mfma_layout(R, CH, D, nb, NW);
+    static_assert(!NCC || (CH == 1 && !FEAT && !CO), "NCC tiles: gray, slab path");
+    const MfmaLayout lay = mfma_layout(R, CH, D, nb, NW, NCC);
     const int RWB = lay.rwb;
     const float* s_gr = reinterpret_cast<const float*>(smem) + 255;  // index by I_q - I_p
     const float* s_gs = s_gr - 255 + kLutN;
@@ -351,6 +399,10 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     uint8_t* s_R = smem + lay.off_R;
     uint16_t* s_L4 = reinterpret_cast<uint16_t*>(smem + lay.off_L4);
     _Float16* s_cost = reinterpret_cast<_Float16*>(smem + lay.off_cost);
+    NccTile nt{smem + lay.off_nL, smem + lay.off_nR,
+               reinterpret_cast<const int*>(smem + lay.off_sl), reinterpret_cast<const double*>(smem + lay.off_rl),
+               reinterpret_cast<const int*>(smem + lay.off_sr), reinterpret_cast<const double*>(smem + lay.off_rr),
+               lay.nlw, lay.nrw, lay.sw, LW, g.ncc_r};
 
     const int lane = tid & 63, wave = tid >> 6;
     const int X0 = tile_x * kTileW, Y0 = tile_y * kTileH;
@@ -380,12 +432,12 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
         // in-bounds addresses instead of branching.  4 bytes per thread and
         // iteration (gray: 4 pixels; RGB: one pixel and a zero byte), all loads
         // issued before the LDS writes.  The left tile also goes to s_L4.
-        auto stage = [&](uint8_t* dst, int wb, int x0, const uint8_t* src, auto words_c) {
-            const int n4 = LH * wb / 4;
+        auto stage = [&](uint8_t* dst, int wb, int nrows, int x0, int y0, const uint8_t* src, auto words_c) {
+            const int n4 = nrows * wb / 4;
 #pragma unroll 2
             for (int i = tid; i < n4; i += kThreads) {
                 const int row = (4 * i) / wb, cb = 4 * i - row * wb;
-                const size_t rbase = (size_t)min(max(oy + row, 0), g.H - 1) * g.stride;
+                const size_t rbase = (size_t)min(max(y0 + row, 0), g.H - 1) * g.stride;
                 uint32_t v = 0;
                 if constexpr (CH == 1) {
 #pragma unroll
@@ -407,10 +459,41 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                 }
             }
         };
-        stage(s_L, LWB, ox, Lg, std::true_type{});
-        stage(s_R, RWB, rox, Rg, std::false_type{});
+        stage(s_L, LWB, LH, ox, oy, Lg, std::true_type{});
+        if constexpr (NCC) {
+            // NCC blocks reach one pixel past the union and the strip; clamped
+            // reads give the clamp-to-edge block coordinates
+            stage(smem + lay.off_nL, lay.nlw, LH + 2, ox - 1, oy - 1, Lg, std::false_type{});
+            stage(smem + lay.off_nR, lay.nrw, LH + 2, rox - 1, oy - 1, Rg, std::false_type{});
+        } else {
+            stage(s_R, RWB, LH, rox, oy, Rg, std::false_type{});
+        }
     }
     __syncthreads();
+    if constexpr (NCC) {
+        // block sum s and 1 / sqrt(n * sum I^2 - s^2) of every union position
+        // and strip column (read after the barrier that opens the first slab)
+        const int nr = g.ncc_r, nn = (2 * nr + 1) * (2 * nr + 1);
+        auto terms = [&](const uint8_t* img, int wb, int w, int cnt, int* so, double* ro) {
+            for (int i = tid; i < cnt; i += kThreads) {
+                const int v = i / w, u = i - v * w;
+                int s1 = 0, s2 = 0;
+                for (int jr = 1 - nr; jr <= 1 + nr; ++jr)
+                    for (int jc = 1 - nr; jc <= 1 + nr; ++jc) {
+                        const int b = img[(v + jr) * wb + u + jc];
+                        s1 += b;
+                        s2 += b * b;
+                    }
+                const int var = nn * s2 - s1 * s1;
+                so[i] = s1;
+                ro[i] = var > 0 ? 1.0 / sqrt((double)var) : 0.0;
+            }
+        };
+        terms(nt.nL, lay.nlw, LW, LH * LW, reinterpret_cast<int*>(smem + lay.off_sl),
+              reinterpret_cast<double*>(smem + lay.off_rl));
+        terms(nt.nR, lay.nrw, lay.sw, LH * lay.sw, reinterpret_cast<int*>(smem + lay.off_sr),
+              reinterpret_cast<double*>(smem + lay.off_rr));
+    }
 
     // ---- this wave's group and this lane's pixel / octet group ----
     const int gcol0 = (wave % C.GX) * GW, grow0 = (wave / C.GX) * GH;  // in the tile
@@ -511,7 +594,8 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     for (int j = 0; j < 8; ++j) ones[j] = (_Float16)1.0f;
     f4 dh = {0.f, 0.f, 0.f, 0.f}, dl = {0.f, 0.f, 0.f, 0.f};
     float rden = 0.0f;  // 1 / Eq. 6's denominator
-    const float inv_scale = 1.0f / (CH == 3 ? 3.0f : 1.0f);
+    // the kernel's cost units: RGB sums 3 channels; NCC costs are scaled by 2^10
+    const float inv_scale = NCC ? 1.0f / 1024.0f : 1.0f / (CH == 3 ? 3.0f : 1.0f);
     if constexpr (!CO) {
         if (want_den) {
 #pragma unroll
@@ -601,7 +685,70 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                         if (j < thr) out[j] = hcap;
                 }
             };
-            if constexpr (CH == 1) {
+            if constexpr (NCC) {
+                // NCC (Eq. 1) at the 8 positions u = 8*oc + j and disparities d0 + jm:
+                // cross terms by byte dot products over the block rows (bordered
+                // tiles: position u is bordered column u + 1, and its block
+                // columns u .. u + 2 are one dword with the fourth byte masked);
+                // right block of (j, jm) at bordered strip columns rb + i .. + 2,
+                // i = j - jm + 3.  Cost 1 - num * rl * rr in double, rounded to
+                // float, scaled by 2^10 and split into fp16 hi + lo planes.
+                const int nr = g.ncc_r, nn = (2 * nr + 1) * (2 * nr + 1);
+                const uint32_t bmask = nr ? 0x00ffffffu : 0x0000ff00u;
+                const int rb = 8 * oc + (dmax - d0 - 3);
+                int slr[4][8];
+#pragma unroll
+                for (int jm = 0; jm < 4; ++jm)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) slr[jm][j] = 0;
+#pragma unroll 1
+                for (int jr = 1 - nr; jr <= 1 + nr; ++jr) {
+                    const uint32_t* lw = reinterpret_cast<const uint32_t*>(nt.nL + (row + jr) * lay.nlw + 8 * oc);
+                    const uint32_t a0 = lw[0], a1 = lw[1], a2 = lw[2];
+                    uint32_t lb[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const uint32_t lo = j < 4 ? a0 : a1, hi = j < 4 ? a1 : a2;
+                        lb[j] = ((j & 3) ? __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)(j & 3)) : lo) & bmask;
+                    }
+                    const int cb = (row + jr) * lay.nrw + rb;
+                    const int ab = cb & ~3;
+                    const uint32_t sh = (uint32_t)(cb - ab);
+                    const uint32_t* wq = reinterpret_cast<const uint32_t*>(nt.nR + ab);
+                    const uint32_t w0 = wq[0], w1 = wq[1], w2 = wq[2], w3 = wq[3];
+                    const uint32_t u[4] = {__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh),
+                                           __builtin_amdgcn_alignbyte(w3, w2, sh), w3 >> (8 * sh)};
+                    uint32_t rw[11];
+#pragma unroll
+                    for (int i = 0; i < 11; ++i)
+                        rw[i] = (i & 3) ? __builtin_amdgcn_alignbyte(u[(i >> 2) + 1], u[i >> 2], (uint32_t)(i & 3)) : u[i >> 2];
+#pragma unroll
+                    for (int jm = 0; jm < 4; ++jm)
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            slr[jm][j] = (int)__builtin_amdgcn_udot4(lb[j], rw[j - jm + 3], (uint32_t)slr[jm][j], false);
+                }
+                const int pbase = row * LW + 8 * oc, sbase = row * lay.sw + rb;
+#pragma unroll
+                for (int jm = 0; jm < 4; ++jm) {
+                    const int d = d0 + jm;
+                    h8 hv, lv;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int i = j - jm + 3;
+                        // a right pixel left of the image (and a padded disparity) costs 2
+                        const bool valid = x0 + j - d >= 0 && d <= dmax;
+                        const int num = nn * slr[jm][j] - nt.sl[pbase + j] * nt.sr[sbase + i];
+                        const double c = 1.0 - (double)num * nt.rl[pbase + j] * nt.rr[sbase + i];
+                        const float cs = (valid ? (float)c : 2.0f) * 1024.0f;
+                        const _Float16 h = (_Float16)cs;
+                        hv[j] = h;
+                        lv[j] = (_Float16)(cs - (float)h);
+                    }
+                    *reinterpret_cast<h8*>(dst + (16 * (quad >> 2) + jm) * PS) = hv;
+                    *reinterpret_cast<h8*>(dst + (16 * (quad >> 2) + 16 + jm) * PS) = lv;
+                }
+            } else if constexpr (CH == 1) {
                 const uint2 lv = *reinterpret_cast<const uint2*>(s_L + row * LWB + 8 * oc);
                 const h2 l[4] = {bytes01_f16(lv.x), bytes23_f16(lv.x), bytes01_f16(lv.y), bytes23_f16(lv.y)};
                 // bytes c0 .. c11 of strip columns from 8*oc + dmax - d0 - 3 on
@@ -672,13 +819,14 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
 
     // WTA (and agg_out / features) over the 4 rows j of one 16-disparity
     // block: lane holds rows 4*gq + j of the 16x16 result, i.e. disparity
-    // index k = kb + j of pixel n
-    auto wta_block = [&](int kb, const f4& acc_h, const f4& acc_l) {
+    // index k = kb + j of pixel n; acc is the sum of the block's chains (TAD:
+    // hi + lo weights; NCC: (hi + lo weights on hi costs) + hi weights on lo costs)
+    auto wta_block = [&](int kb, const f4& acc) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int k = kb + j;
             if (k < D) {
-                const float v = acc_h[j] + acc_l[j];
+                const float v = acc[j];
                 if (k == gq * Q) first_v = v;
                 last_v = v;
                 const bool lt = v < best;
@@ -706,7 +854,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = kb + j;
-                const float a = ((acc_h[j] + acc_l[j]) * rden) * inv_scale;
+                const float a = (acc[j] * rden) * inv_scale;
                 bk[j] = k < D ? (__float_as_uint(a) & ~kmask) | (uint32_t)k : ~0u;
             }
             ce(bk[0], bk[1]);
@@ -767,7 +915,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
             if (den_on) rden = 1.0f / (dh[0] + dl[0]);
 #pragma unroll
             for (int b = 0; b < kCoMax; ++b)
-                if (NBK ? b < NBK : b < nblk) wta_block(gq * Q + 4 * b, ah[b], al[b]);
+                if (NBK ? b < NBK : b < nblk) wta_block(gq * Q + 4 * b, ah[b] + al[b]);
         };
         using I0 = std::integral_constant<int, 0>;
         using I1 = std::integral_constant<int, 1>;
@@ -794,22 +942,36 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
             // matrix instructions; an odd last block runs alone
             auto blocks = [&](int bb, auto two_c) {
                 constexpr bool TWO = decltype(two_c)::value;
-                f4 ah0 = {0.f, 0.f, 0.f, 0.f}, al0 = ah0, ah1 = ah0, al1 = ah0;
-                const _Float16* p0 = plane0 + (size_t)(16 * bb) * PS;
-                const _Float16* p1 = p0 + (size_t)16 * PS;
+                constexpr int kPlanes = NCC ? 32 : 16;  // planes per block (NCC: hi, then lo costs)
+                f4 ah0 = {0.f, 0.f, 0.f, 0.f}, al0 = ah0, ah1 = ah0, al1 = ah0, am0 = ah0, am1 = ah0;
+                const _Float16* p0 = plane0 + (size_t)(kPlanes * bb) * PS;
+                const _Float16* p1 = p0 + (size_t)kPlanes * PS;
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     const h8 a0 = lds_h8<GW == 8>(p0 + a_off(c));
                     ah0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, whi[c], ah0, 0, 0, 0);
                     al0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, wlo[c], al0, 0, 0, 0);
+                    if constexpr (NCC) {
+                        const h8 m0 = lds_h8<GW == 8>(p0 + (size_t)16 * PS + a_off(c));
+                        am0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(m0, whi[c], am0, 0, 0, 0);
+                    }
                     if constexpr (TWO) {
                         const h8 a1 = lds_h8<GW == 8>(p1 + a_off(c));
                         ah1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, whi[c], ah1, 0, 0, 0);
                         al1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, wlo[c], al1, 0, 0, 0);
+                        if constexpr (NCC) {
+                            const h8 m1 = lds_h8<GW == 8>(p1 + (size_t)16 * PS + a_off(c));
+                            am1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(m1, whi[c], am1, 0, 0, 0);
+                        }
                     }
                 }
-                wta_block(gq * Q + 4 * (b0 + bb), ah0, al0);
-                if constexpr (TWO) wta_block(gq * Q + 4 * (b0 + bb + 1), ah1, al1);
+                if constexpr (NCC) {
+                    wta_block(gq * Q + 4 * (b0 + bb), (ah0 + al0) + am0);
+                    if constexpr (TWO) wta_block(gq * Q + 4 * (b0 + bb + 1), (ah1 + al1) + am1);
+                } else {
+                    wta_block(gq * Q + 4 * (b0 + bb), ah0 + al0);
+                    if constexpr (TWO) wta_block(gq * Q + 4 * (b0 + bb + 1), ah1 + al1);
+                }
             };
             int bb = 0;
 #pragma unroll 1
@@ -868,8 +1030,8 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
         recheck &= recheck - 1;
         int rk;
         float rds;
-        recheck_pixel<R, CH>(job, s_L, s_R, LWB, RWB, grow0 + n0 / GW, gcol0 + n0 % GW, X0, Y0,
-                             lane, rk, rds);
+        recheck_pixel<R, CH, NCC>(job, s_L, s_R, LWB, RWB, grow0 + n0 / GW, gcol0 + n0 % GW, X0, Y0,
+                             lane, rk, rds, nt);
         if (lane == n0) {
             fix_k = rk;
             fix_ds = rds;
@@ -944,6 +1106,16 @@ __global__ __launch_bounds__(64 * NW) void k_fbs_mfma(TileJob job, Tables tb)
     load_tables(tb, R, smem, 64 * NW);
     __syncthreads();
     mfma_tile<R, CH, NW, false, CO>(job, blockIdx.x, blockIdx.y, smem, threadIdx.x);
+}
+
+// One workgroup per tile of one gray frame with the NCC cost (slab path).
+template <int R, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fbs_mfma_ncc(TileJob job, Tables tb)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    load_tables(tb, R, smem, 64 * NW);
+    __syncthreads();
+    mfma_tile<R, 1, NW, false, false, true>(job, blockIdx.x, blockIdx.y, smem, threadIdx.x);
 }
 
 // One workgroup per tile of one gray frame, with the surrogate's features.
@@ -1045,11 +1217,11 @@ inline int deepest_nb(const Geom& g, int nw, int budget)
     return nb;
 }
 
-inline int max_nb(int r, int ch, int D, int nw)
+inline int max_nb(int r, int ch, int D, int nw, bool ncc = false)
 {
     const int nblk = (D + 15) >> 4;
     int nb = 1;
-    while (nb < nblk && nb < kMaxNb && mfma_layout(r, ch, D, nb + 1, nw).bytes <= kLdsLimit) ++nb;
+    while (nb < nblk && nb < kMaxNb && mfma_layout(r, ch, D, nb + 1, nw, ncc).bytes <= kLdsLimit) ++nb;
     return nb;
 }
 
@@ -1071,6 +1243,26 @@ hipError_t launch_frame(const TileJob& job, const Tables& t, hipStream_t s)
         hipLaunchKernelGGL((k_fbs_mfma<R, CH, NW, false>), grid, dim3(64 * NW), lay.bytes, s, job, t);
     return hipGetLastError();
 }
+
+// NCC frames: gray tiles of 4 waves, or of 8 up to r = kNccMaxR8 (at r = 10
+// the 8-wave NCC tile spills: the weights and the cross terms of the cost
+// build do not fit 256 registers together)
+constexpr int kNccMaxR8 = 9;
+template <int R, int CH, int NW>
+struct NccLauncher {
+    static hipError_t run(const TileJob& job, const Tables& t, hipStream_t s)
+    {
+        if constexpr (CH != 1 || NW == 12 || (NW == 8 && R > kNccMaxR8)) {
+            return hipErrorInvalidValue;
+        } else {
+            const MfmaLayout lay = mfma_layout(R, 1, job.g.D, job.nb, NW, true);
+            if (lay.bytes > kLdsLimit) return hipErrorInvalidConfiguration;
+            dim3 grid((job.g.W + 2 * NW - 1) / (2 * NW), (job.g.H + kTileH - 1) / kTileH);
+            hipLaunchKernelGGL((k_fbs_mfma_ncc<R, NW>), grid, dim3(64 * NW), lay.bytes, s, job, t);
+            return hipGetLastError();
+        }
+    }
+};
 
 template <int R, int CH, int NW>
 struct FeatOccupancy {
