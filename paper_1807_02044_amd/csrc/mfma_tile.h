@@ -103,9 +103,11 @@ struct MfmaLayout {
     int bytes;
 };
 
-// Left tile again as 16-bit words 4 * I per channel (RGB: R, G, B, 0): the
-// byte offsets of the range factors, so that a factor's address is one add.
-__host__ __device__ constexpr int pixel_words(int ch) { return ch == 3 ? 4 : 1; }
+// RGB: the left tile again as 16-bit words 4 * I per channel (R, G, B, 0),
+// the byte offsets of the range factors, so that each of a weight's three
+// factor addresses is one add.  (Gray keeps its byte tile: one address per
+// weight, and small gray tiles stay within half the LDS.)
+__host__ __device__ constexpr int pixel_words(int ch) { return ch == 3 ? 4 : 0; }
 
 // Bytes per pixel in the LDS image rows: gray 1; RGB 4 (R, G, B, 0), so that a
 // pixel is one aligned dword for the byte-wise SAD and the range weights.
@@ -452,14 +454,14 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                 }
                 reinterpret_cast<uint32_t*>(dst)[i] = v;
                 if constexpr (decltype(words_c)::value) {
-                    // the same 4 bytes (gray: 4 pixels; RGB: R, G, B, 0) as 4 * byte in 16-bit words
+                    // the same pixel (R, G, B, 0) as 4 * byte in 16-bit words
                     const uint32_t w0 = ((v & 0xffu) | ((v & 0xff00u) << 8)) << 2;
-                    const uint32_t w1 = (((v >> 16) & 0xffu) | ((v >> 8) & 0xff0000u)) << 2;
+                    const uint32_t w1 = ((v >> 16) & 0xffu) << 2;
                     reinterpret_cast<uint2*>(s_L4)[i] = make_uint2(w0, w1);
                 }
             }
         };
-        stage(s_L, LWB, LH, ox, oy, Lg, std::true_type{});
+        stage(s_L, LWB, LH, ox, oy, Lg, std::integral_constant<bool, CH == 3>{});
         if constexpr (NCC) {
             // NCC blocks reach one pixel past the union and the strip; clamped
             // reads give the clamp-to-edge block coordinates
@@ -508,7 +510,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) lp[ch] = s_L[(prow + R) * LWB + (pcol + R) * PB + ch];
     // range factor of channel ch for a neighbour of intensity I: the float at
-    // byte offset 4 * I from gb[ch]
+    // byte offset 4 * I from gb[ch] (RGB), s_gr[I - lp[0]] (gray)
     const uint8_t* gb[CH];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) gb[ch] = reinterpret_cast<const uint8_t*>(s_gr - (int)lp[ch]);
@@ -522,17 +524,24 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
         const float4 wx0 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U);
         const float4 wx1 = *reinterpret_cast<const float4*>(s_wx + pcol * LW + U + 4);
         const float wx[8] = {wx0.x, wx0.y, wx0.z, wx0.w, wx1.x, wx1.y, wx1.z, wx1.w};
-        // 8 pixels of the left image as words 4 * I (U is a multiple of 8)
+        // 8 pixels of the left image (U is a multiple of 8): RGB as words 4 * I,
+        // gray as bytes
         constexpr int PW = pixel_words(CH);
-        uint32_t lq[4 * PW];
-        const uint4* q = reinterpret_cast<const uint4*>(s_L4 + (V * LW + U) * PW);
+        uint32_t lq[CH == 3 ? 4 * PW : 2];
+        if constexpr (CH == 3) {
+            const uint4* q = reinterpret_cast<const uint4*>(s_L4 + (V * LW + U) * PW);
 #pragma unroll
-        for (int i = 0; i < PW; ++i) {
-            const uint4 t = q[i];
-            lq[4 * i] = t.x;
-            lq[4 * i + 1] = t.y;
-            lq[4 * i + 2] = t.z;
-            lq[4 * i + 3] = t.w;
+            for (int i = 0; i < PW; ++i) {
+                const uint4 t = q[i];
+                lq[4 * i] = t.x;
+                lq[4 * i + 1] = t.y;
+                lq[4 * i + 2] = t.z;
+                lq[4 * i + 3] = t.w;
+            }
+        } else {
+            const uint2 t = *reinterpret_cast<const uint2*>(s_L + V * LWB + U);
+            lq[0] = t.x;
+            lq[1] = t.y;
         }
         float wa[8], wb[8];  // w = wa * wb
 #pragma unroll
@@ -540,9 +549,15 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
             float wr = 1.0f;
 #pragma unroll
             for (int ch = 0; ch < CH; ++ch) {
-                const int wi = PW * j + ch;  // word index
-                const uint32_t off = (wi & 1) ? lq[wi >> 1] >> 16 : lq[wi >> 1] & 0xffffu;
-                const float f = *reinterpret_cast<const float*>(gb[ch] + off);
+                float f;
+                if constexpr (CH == 3) {
+                    const int wi = PW * j + ch;  // word index
+                    const uint32_t off = (wi & 1) ? lq[wi >> 1] >> 16 : lq[wi >> 1] & 0xffffu;
+                    f = *reinterpret_cast<const float*>(gb[ch] + off);
+                } else {
+                    const int iv = (int)((lq[j >> 2] >> (8 * (j & 3))) & 0xffu);
+                    f = s_gr[iv - (int)lp[0]];
+                }
                 wr = ch == 0 ? f : wr * f;
             }
             wa[j] = wx[j] * wy;
