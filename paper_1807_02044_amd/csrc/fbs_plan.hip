@@ -67,7 +67,9 @@ std::string shape_key(const fbs::Geom& g)
     return b;
 }
 
-// ---- tuning cache: {"arch": "gfx950", "entries": {"W,H,C,D,r": [nw, nb, us], ...}}
+// ---- tuning cache: {"arch": "gfx950", "entries": {"W,H,C,D,r": [nw, nb, us, "path"], ...}}
+// where path names the loop order the depth implies: "chunk-outer" (one slab
+// holds every disparity block) or "slab"; a reader needs only the first three
 struct TuneEntry {
     int nw, nb;
     double us;
@@ -112,8 +114,11 @@ void write_cache(const char* path, const std::map<std::string, TuneEntry>& m)
     fprintf(f, "{\"arch\": \"gfx950\", \"entries\": {");
     bool first = true;
     for (const auto& kv : m) {
-        fprintf(f, "%s\n  \"%s\": [%d, %d, %.3f]", first ? "" : ",", kv.first.c_str(), kv.second.nw,
-                kv.second.nb, kv.second.us);
+        int D = 0;
+        (void)sscanf(kv.first.c_str(), "%*d,%*d,%*d,%d", &D);
+        const bool co = fbs::mfma_use_co(D, kv.second.nb);
+        fprintf(f, "%s\n  \"%s\": [%d, %d, %.3f, \"%s\"]", first ? "" : ",", kv.first.c_str(),
+                kv.second.nw, kv.second.nb, kv.second.us, co ? "chunk-outer" : "slab");
         first = false;
     }
     fprintf(f, "\n}}\n");

@@ -104,8 +104,11 @@ def test_plan_tuning_cache_roundtrip(tmp_path):
     plan.close()
     data = json.load(open(cache))
     assert data["arch"] == "gfx950" and len(data["entries"]) == 3
-    for key, (nw, nb, us) in data["entries"].items():
+    for key, (nw, nb, us, path) in data["entries"].items():
         assert nw in (4, 8, 12) and nb >= 1 and us > 0
+        # the loop order the depth implies: chunk-outer when one slab holds every block
+        nblk = (int(key.split(",")[3]) + 15) // 16
+        assert path == ("chunk-outer" if nb == nblk and nblk <= 6 else "slab")
     # a plan built from the cache alone picks the same configurations
     plan2 = L.FbsPlan(params, tune_cache=cache, tune=False)
     assert [plan2.pair_config(i) for i in range(3)] == tuned
