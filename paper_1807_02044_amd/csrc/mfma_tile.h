@@ -624,7 +624,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
 
     // ---- running WTA over this lane's quarter of the disparity range ----
     const float kInf = __builtin_inff();
-    float best = kInf, cm = kInf, cp = kInf, prev = kInf, first_v = kInf, last_v = kInf;
+    float best = kInf, cm = kInf, cp = kInf, prev = kInf, first_v = kInf;
     float best2 = kInf;  // second-lowest value of this lane's quarter (near-tie check)
     int bi = -1;
     bool need_cp = false;
@@ -837,28 +837,30 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     // index k = kb + j of pixel n; acc is the sum of the block's chains (TAD:
     // hi + lo weights; NCC: (hi + lo weights on hi costs) + hi weights on lo costs)
     auto wta_block = [&](int kb, const f4& acc) {
+        if (agg && pin) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (kb + j < D)
+                    agg[(size_t)(kb + j) * g.W * g.H + (size_t)py * g.W + px] = (acc[j] * rden) * inv_scale;
+        }
+        // The running first minimum as selects, no branches.  A padded
+        // disparity (k >= D) enters as +inf: it never wins, leaves the second
+        // lowest alone, and only ever follows the quarter's real values.
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int k = kb + j;
-            if (k < D) {
-                const float v = acc[j];
-                if (k == gq * Q) first_v = v;
-                last_v = v;
-                const bool lt = v < best;
-                if (lt) {
-                    best2 = best;
-                    cm = prev;
-                    best = v;
-                    bi = k;
-                } else {
-                    if (need_cp) cp = v;
-                    best2 = fminf(best2, v);
-                }
-                need_cp = lt;
-                prev = v;
-                if (agg && pin)
-                    agg[(size_t)k * g.W * g.H + (size_t)py * g.W + px] = (v * rden) * inv_scale;
-            }
+            const float v = k < D ? acc[j] : kInf;
+            if (j == 0 && kb == gq * Q) first_v = v;
+            const bool lt = v < best;
+            // best2 >= best always, so this is best when v < best, else
+            // min(best2, v); and min(best, v) keeps best on a tie
+            best2 = fminf(fmaxf(best, v), best2);
+            best = fminf(best, v);
+            cp = (!lt && need_cp) ? v : cp;
+            cm = lt ? prev : cm;
+            bi = lt ? k : bi;
+            need_cp = lt;
+            prev = v;  // after the last block: the quarter's last value
         }
         if constexpr (FEAT) {
             // the block's four keys, sorted, then merged into the running
@@ -1001,7 +1003,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     float wv = __shfl(best, n), wm = __shfl(cm, n), wp = __shfl(cp, n);
     int wk = __shfl(bi, n), wc = __shfl((int)need_cp, n), wt = 0;
     float left_last = kInf;   // last value of the quarter before the winner
-    float prev_last = __shfl(last_v, n);
+    float prev_last = __shfl(prev, n);
     float qb[4], qs[4];       // each quarter's lowest and second-lowest value
     qb[0] = wv;
     qs[0] = __shfl(best2, n);
@@ -1019,7 +1021,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
             wv = tv; wk = tk; wm = tm; wp = tp; wc = tc; wt = t;
             left_last = prev_last;
         }
-        prev_last = __shfl(last_v, src);
+        prev_last = __shfl(prev, src);
     }
     // first value of the quarter after the winner
     const float right_first = __shfl(first_v, n + 16 * min(wt + 1, 3));
