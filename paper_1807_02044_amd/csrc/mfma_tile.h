@@ -52,6 +52,7 @@ constexpr int kTileH = 8;         // tile rows; a tile is kTileH x (2 * waves) p
 constexpr float kWScale = 16384.0f;  // 2^14: keeps small weights in fp16's normal range
 constexpr int kMaxR = 10;
 constexpr int kCoMax = 6;  // chunk-outer path: at most this many 16-disparity blocks
+constexpr int kMaxNbAll = 64;  // bound on the 16-disparity blocks of one slab (FBS_MAX_DISP / 16)
 // range factor by signed intensity difference -255..255 (no abs per weight),
 // padded to a multiple of 4 floats
 constexpr int kLutN = 512;
@@ -390,9 +391,11 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     const int D = g.D;
     const int nblk = (D + 15) >> 4;   // 16-disparity blocks
     const int Q = nblk * 4;           // disparities per lane group
+    __builtin_assume(Q > 0 && Q <= 4 * kMaxNbAll);
     static_assert(!NCC || (CH == 1 && !FEAT && !CO), "NCC tiles: gray, slab path");
     const MfmaLayout lay = mfma_layout(R, CH, D, nb, NW, NCC);
     const int RWB = lay.rwb;
+    __builtin_assume(RWB >= 0 && RWB < 65536);
     const float* s_gr = reinterpret_cast<const float*>(smem) + 255;  // index by I_q - I_p
     const float* s_gs = s_gr - 255 + kLutN;
     float* s_wx = reinterpret_cast<float*>(smem + lay.off_wx);
@@ -686,6 +689,9 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
         int pair = b_p0, quad = b_q0;
 #pragma unroll 1
         while (quad < 4 * nbb) {
+            // small ranges: lets the address arithmetic use 24-bit multiplies
+            __builtin_assume(pair >= 0 && pair < kPairs);
+            __builtin_assume(quad >= 0 && quad < 4 * kMaxNbAll);
             const int row = pair / kOct, oc = pair - row * kOct;
             const int x0 = ox + 8 * oc;
             const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
