@@ -37,9 +37,9 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0     # dense fp16 matrix peak
 MEASURED_TRAFFIC = {
     "rich25_1400x1000_rgb_d0-159_r10": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "479b7bf23ac0f5b107a6dcd263472d978f3290e3ef3934e2859f3d59ebf5e03c",
-        # FETCH_SIZE 27090.7 KiB x 2.0 + WRITE_SIZE 10937.5 KiB x 1.0
-        "bytes_per_launch": 66.68e6,
+        "sha256": "f74d3fafb5274e0eb7d4cf41ab7c3406b5fe3bcba352016e59ecca2f5c16886a",
+        # FETCH_SIZE 27086.2 KiB x 2.0 + WRITE_SIZE 10937.5 KiB x 1.0
+        "bytes_per_launch": 66.67e6,
     },
 }
 
@@ -50,21 +50,21 @@ MEASURED_TRAFFIC = {
 MEASURED_UTIL = {
     "rich25_1400x1000_rgb_d0-159_r10": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "479b7bf23ac0f5b107a6dcd263472d978f3290e3ef3934e2859f3d59ebf5e03c",
+        "sha256": "f74d3fafb5274e0eb7d4cf41ab7c3406b5fe3bcba352016e59ecca2f5c16886a",
         # SQ_INSTS_VALU x 4 cycles and SQ_VALU_MFMA_BUSY_CYCLES over the SIMD-cycles
-        # of a 1.483 ms launch (1024 SIMDs at 2.4 GHz); SQ_LDS_BANK_CONFLICT over
+        # of a 1.408 ms launch (1024 SIMDs at 2.4 GHz); SQ_LDS_BANK_CONFLICT over
         # SQ_LDS_IDX_ACTIVE
-        "valu_issue_frac": 0.477,
-        "mfma_busy_frac": 0.139,
+        "valu_issue_frac": 0.449,
+        "mfma_busy_frac": 0.147,
         "lds_bank_conflict_frac": 0.385,
-        "counters_kernel_avg_ms": 1.483,
+        "counters_kernel_avg_ms": 1.408,
     },
     "slanted8_450x375_gray_d0-63_r7": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "479b7bf23ac0f5b107a6dcd263472d978f3290e3ef3934e2859f3d59ebf5e03c",
-        "valu_issue_frac": 0.548,
-        "mfma_busy_frac": 0.128,
-        "counters_kernel_avg_ms": 0.05250,
+        "sha256": "f74d3fafb5274e0eb7d4cf41ab7c3406b5fe3bcba352016e59ecca2f5c16886a",
+        "valu_issue_frac": 0.532,
+        "mfma_busy_frac": 0.135,
+        "counters_kernel_avg_ms": 0.04971,
     },
 }
 
