@@ -597,6 +597,84 @@ def guided(args, dev):
             "mean_range_width": float(np.mean(width))}
 
 
+def guided_headline(args, dev, wl, pair):
+    """The guided-range pipeline on the headline pair (wider disparity range):
+    seeds from a radius-3 left-right run of the same pair, per-tile ranges
+    (halo = the full radius, margin 3), the full-radius run over the ranges;
+    against the plain full-range run.  Per-stage times from HIP events on the
+    pipeline's stream."""
+    import torch
+    from paper_1807_02044_amd import _lib as L
+    import paper_1807_02044_amd as fbs
+    pf = fbs.params_for(wl)
+    pc = fbs.params_for(wl.with_(radius=3, sigma_s=3.0))
+    Ld = torch.from_numpy(pair.left).to(dev)
+    Rd = torch.from_numpy(pair.right).to(dev)
+    H, W = wl.height, wl.width
+    tw, th = L.fbs_range_tile(pf)
+    dl = torch.empty((H, W), dtype=torch.int32, device=dev)
+    valid = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    ws = torch.empty(L.fbs_lr_workspace_bytes(pc), dtype=torch.uint8, device=dev)
+    rg = torch.empty(((H + th - 1) // th, (W + tw - 1) // tw, 2), dtype=torch.int32, device=dev)
+    plain = torch.empty((H, W), dtype=torch.float32, device=dev)
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    halo, margin = wl.radius, 3
+    stream = torch.cuda.Stream(device=dev)
+    steps = max(3, args.lr_steps)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def run_plain():
+        L.fbs_run(pf, Ld, Rd, None, plain, None, None, stream)
+
+    def run_guided(marks=None):
+        if marks:
+            marks[0].record(stream)
+        L.fbs_run_lr(pc, Ld, Rd, 0, dl, None, valid, None, ws, stream)
+        if marks:
+            marks[1].record(stream)
+        L.fbs_guided_ranges(pf, dl, valid, halo, margin, rg, stream)
+        if marks:
+            marks[2].record(stream)
+        L.fbs_run_ranged(pf, Ld, Rd, rg, None, out, stream)
+        if marks:
+            marks[3].record(stream)
+
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                fn()
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            stream.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t_plain = timed(run_plain)
+    t_guided = timed(run_guided)
+    stages = [[], [], []]
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            m = [ev() for _ in range(4)]
+            run_guided(m)
+            stream.synchronize()
+            for k in range(3):
+                stages[k].append(m[k].elapsed_time(m[k + 1]))
+        run_plain()
+        stream.synchronize()
+    bad = float(((out - plain).abs() > 1.0).float().mean().item())
+    width = float((rg[..., 1] - rg[..., 0] + 1).float().mean().item())
+    return {"workload": wl.name, "steps": steps, "halo": halo, "margin": margin,
+            "tile": [tw, th], "seed_radius": 3,
+            "plain_frames_per_s": 1.0 / t_plain, "guided_frames_per_s": 1.0 / t_guided,
+            "speedup_vs_plain": t_plain / t_guided,
+            "seeds_ms": sum(stages[0]) / steps, "ranges_ms": sum(stages[1]) / steps,
+            "ranged_run_ms": sum(stages[2]) / steps,
+            "bad1_vs_plain": bad, "mean_range_width": width}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -721,6 +799,7 @@ def main():
         out["left_right"] = left_right(args, dev, wl, pair)
     if not args.no_guided:
         out["guided"] = guided(args, dev)
+        out["guided"]["headline_pair"] = guided_headline(args, dev, wl, pair)
     if not args.no_batched:
         out["batched"] = batched(args, dev)
     if not args.no_surrogate:
