@@ -33,12 +33,12 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0     # dense fp16 matrix peak
 
 # HBM bytes per launch of the fused kernel from two rocprofv3 PMC runs
 # (FETCH_SIZE, WRITE_SIZE), each scaled by what the counter reads for a
-# 256 MiB device copy.  Valid only for the kernel source they were taken on.
+# 1 GiB device copy.  Valid only for the kernel source they were taken on.
 MEASURED_TRAFFIC = {
     "rich25_1400x1000_rgb_d0-159_r10": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "f74d3fafb5274e0eb7d4cf41ab7c3406b5fe3bcba352016e59ecca2f5c16886a",
-        # FETCH_SIZE 27086.2 KiB x 2.0 + WRITE_SIZE 10937.5 KiB x 1.0
+        "sha256": "722f3d19db9c4dbebde28cf1ab4c3d0967d13477ab884b30b0e2db98861bb675",
+        # FETCH_SIZE 27086.7 KiB x 2.0 + WRITE_SIZE 10937.5 KiB x 1.0
         "bytes_per_launch": 66.67e6,
     },
 }
@@ -50,21 +50,21 @@ MEASURED_TRAFFIC = {
 MEASURED_UTIL = {
     "rich25_1400x1000_rgb_d0-159_r10": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "f74d3fafb5274e0eb7d4cf41ab7c3406b5fe3bcba352016e59ecca2f5c16886a",
+        "sha256": "722f3d19db9c4dbebde28cf1ab4c3d0967d13477ab884b30b0e2db98861bb675",
         # SQ_INSTS_VALU x 4 cycles and SQ_VALU_MFMA_BUSY_CYCLES over the SIMD-cycles
-        # of a 1.408 ms launch (1024 SIMDs at 2.4 GHz); SQ_LDS_BANK_CONFLICT over
+        # of a 1.290 ms launch (1024 SIMDs at 2.4 GHz); SQ_LDS_BANK_CONFLICT over
         # SQ_LDS_IDX_ACTIVE
-        "valu_issue_frac": 0.449,
-        "mfma_busy_frac": 0.147,
-        "lds_bank_conflict_frac": 0.385,
-        "counters_kernel_avg_ms": 1.408,
+        "valu_issue_frac": 0.498,
+        "mfma_busy_frac": 0.160,
+        "lds_bank_conflict_frac": 0.244,
+        "counters_kernel_avg_ms": 1.290,
     },
     "slanted8_450x375_gray_d0-63_r7": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "f74d3fafb5274e0eb7d4cf41ab7c3406b5fe3bcba352016e59ecca2f5c16886a",
-        "valu_issue_frac": 0.532,
-        "mfma_busy_frac": 0.135,
-        "counters_kernel_avg_ms": 0.04971,
+        "sha256": "722f3d19db9c4dbebde28cf1ab4c3d0967d13477ab884b30b0e2db98861bb675",
+        "valu_issue_frac": 0.528,
+        "mfma_busy_frac": 0.134,
+        "counters_kernel_avg_ms": 0.05006,
     },
 }
 

@@ -384,6 +384,13 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
     constexpr Cfg C = cfg_of(R, kTileW);
     constexpr int GH = C.GH, GW = C.GW, OPR = C.OPR, NOCT = C.NOCT, NCH = C.NCH;
     constexpr int LH = C.LH, LW = C.LW, PS = C.PS;
+    // 4x4 groups read their A operands as two 8-byte halves, 16 lanes (rows
+    // m = 0..15 of one K quarter) per LDS cycle; the plane stride is 16 bytes
+    // modulo 128, so rows m and m + 8 would share banks.  Planes 8..15 of
+    // every 16 therefore sit 4 halves (8 bytes) further in their slot (the
+    // slot's pad holds them), and their stores are 8-byte pairs.  2x8 groups
+    // read 16 bytes per lane, 8 lanes per cycle: no shift.
+    constexpr int kShift = GW == 4 ? 4 : 0;
     constexpr int PB = pixel_bytes(CH);  // bytes per pixel in LDS
     constexpr int LWB = PB * LW;
     static_assert(C.GX * C.GY == NW, "one group per wave");
@@ -696,7 +703,16 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
             const int x0 = ox + 8 * oc;
             const int k0 = (quad & 3) * Q + 4 * (b0 + (quad >> 2));
             const int d0 = g.dmin + k0;
-            _Float16* dst = s_cost + (size_t)(4 * quad) * PS + row * LW + 8 * oc;
+            // planes 4 quad + jm (+ 16 k): bit 3 of the plane index is bit 1 of quad
+            _Float16* dst = s_cost + (size_t)(4 * quad) * PS + ((quad & 2) ? kShift : 0) + row * LW + 8 * oc;
+            auto put = [](_Float16* q, const h8& v) {
+                if constexpr (kShift == 0) {
+                    *reinterpret_cast<h8*>(q) = v;
+                } else {
+                    *reinterpret_cast<h4*>(q) = __builtin_shufflevector(v, v, 0, 1, 2, 3);
+                    *reinterpret_cast<h4*>(q + 4) = __builtin_shufflevector(v, v, 4, 5, 6, 7);
+                }
+            };
             // a cost that pairs with a right pixel left of the image is the cap
             auto left_fill = [&](h8& out, int d) {
                 const int thr = d - x0;  // positions j < thr: x - d < 0
@@ -766,8 +782,8 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                         hv[j] = h;
                         lv[j] = (_Float16)(cs - (float)h);
                     }
-                    *reinterpret_cast<h8*>(dst + (16 * (quad >> 2) + jm) * PS) = hv;
-                    *reinterpret_cast<h8*>(dst + (16 * (quad >> 2) + 16 + jm) * PS) = lv;
+                    put(dst + (16 * (quad >> 2) + jm) * PS, hv);
+                    put(dst + (16 * (quad >> 2) + 16 + jm) * PS, lv);
                 }
             } else if constexpr (CH == 1) {
                 const uint2 lv = *reinterpret_cast<const uint2*>(s_L + row * LWB + 8 * oc);
@@ -799,7 +815,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                         out[2 * i + 1] = c[1];
                     }
                     left_fill(out, d0 + jm);
-                    *reinterpret_cast<h8*>(dst + jm * PS) = out;
+                    put(dst + jm * PS, out);
                 }
             } else {
                 const uint4* lq = reinterpret_cast<const uint4*>(s_L + row * LWB + 32 * oc);
@@ -825,7 +841,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
                         out[2 * i + 1] = c[1];
                     }
                     left_fill(out, d0 + jm);
-                    *reinterpret_cast<h8*>(dst + jm * PS) = out;
+                    put(dst + jm * PS, out);
                 }
             }
             // next item: kThreads further in (quad, octet) order
@@ -896,7 +912,7 @@ __device__ __forceinline__ void mfma_tile(const TileJob& job_in, int tile_x, int
         }
     };
 
-    const _Float16* plane0 = s_cost + (size_t)n * PS + grow0 * LW + gcol0;
+    const _Float16* plane0 = s_cost + (size_t)n * PS + ((n & 8) ? kShift : 0) + grow0 * LW + gcol0;
     if constexpr (CO) {
         __syncthreads();
         build_slab(0, nblk);
