@@ -37,7 +37,7 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0     # dense fp16 matrix peak
 MEASURED_TRAFFIC = {
     "rich25_1400x1000_rgb_d0-159_r10": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "722f3d19db9c4dbebde28cf1ab4c3d0967d13477ab884b30b0e2db98861bb675",
+        "sha256": "e61133e20c18c875cf646b532e16ca7437c1a726c31764a60fff1aad25b7b6a1",
         # FETCH_SIZE 27086.7 KiB x 2.0 + WRITE_SIZE 10937.5 KiB x 1.0
         "bytes_per_launch": 66.67e6,
     },
@@ -50,7 +50,7 @@ MEASURED_TRAFFIC = {
 MEASURED_UTIL = {
     "rich25_1400x1000_rgb_d0-159_r10": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "722f3d19db9c4dbebde28cf1ab4c3d0967d13477ab884b30b0e2db98861bb675",
+        "sha256": "e61133e20c18c875cf646b532e16ca7437c1a726c31764a60fff1aad25b7b6a1",
         # SQ_INSTS_VALU x 4 cycles and SQ_VALU_MFMA_BUSY_CYCLES over the SIMD-cycles
         # of a 1.290 ms launch (1024 SIMDs at 2.4 GHz); SQ_LDS_BANK_CONFLICT over
         # SQ_LDS_IDX_ACTIVE
@@ -61,7 +61,7 @@ MEASURED_UTIL = {
     },
     "slanted8_450x375_gray_d0-63_r7": {
         "sources": ["paper_1807_02044_amd/csrc/mfma_tile.h", "paper_1807_02044_amd/csrc/k_mfma.hip"],
-        "sha256": "722f3d19db9c4dbebde28cf1ab4c3d0967d13477ab884b30b0e2db98861bb675",
+        "sha256": "e61133e20c18c875cf646b532e16ca7437c1a726c31764a60fff1aad25b7b6a1",
         "valu_issue_frac": 0.528,
         "mfma_busy_frac": 0.134,
         "counters_kernel_avg_ms": 0.05006,

@@ -68,8 +68,10 @@ struct Cfg {
     int NCH;     // K chunks of 32
     int GX, GY;  // groups across / down the tile
     int LH, LW;  // rows / padded columns of the tile's union
-    // cost plane stride in halves: PS/2 = 4 (mod 64) dwords, so the 16 lanes
-    // reading 16 planes at one offset hit 16 distinct 4-bank groups
+    // cost plane stride in halves: PS/2 = 4 (mod 64) dwords, i.e. 16 bytes
+    // modulo 128, so 8 planes read at one offset (the 8 lanes of one cycle of
+    // a 16-byte read) hit 8 distinct 4-bank groups; 8-byte reads serve 16
+    // lanes per cycle, for which 4x4 groups also shift planes 8-15 (kShift)
     int PS;
 };
 
